@@ -1,0 +1,184 @@
+"""SDC zone-updates/s on one MI355X (Castro, Sec. 2, Eq. 2).
+
+    python bench.py [--steps K] [--warmup W] [--workload net3d] [--precision both]
+
+Default workload: the 3D 256^3 grid with the 13-species / 20-reaction seeded
+network, 3 Gauss-Lobatto nodes (Simpson), K = 4 SDC iterations per step,
+MC slopes and local Rusanov speeds, CFL time step.  A step is one full pass of
+the hot path: 4 iterations x 2 node transitions (fused quadrature, explicit
+update and per-zone Newton) plus the advective term at every new node.  Inputs
+are resident in HBM before the timed region, which brackets exactly K steps
+with device synchronisation.  Prints one JSON line.
+
+The FP64 path gives `value`; the mixed path (FP32 Newton matrix and LU) is
+reported beside it.  `roofline` covers the dominant kernels (the fused
+transition kernels), timed with HIP events on the launch stream inside the
+timed region.  `cpu_baseline` times the CPU oracle on a bounded sub-volume of
+the same workload (single thread).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import sdc_inputs as si  # noqa: E402
+
+PEAK_FP64_TFLOPS = 78.6  # MI355X vector FP64 (FMA counts 2)
+PEAK_HBM_GBS = 8000.0
+
+
+def transition_model(h, work_kinds, stats, nlaunch):
+    """Algorithmic flops and HBM bytes of the transition launches.
+
+    Flops: every Newton iteration costs the residual/matrix assembly, the LU
+    and the triangular solves of the generated code (plus 2 n_r for the
+    update and test); every solve adds one R(x) evaluation and the explicit
+    update (about 4 n_c).  Bytes: each kernel's reads and writes of state,
+    advective, source and correction arrays, once each, in FP64.
+    """
+    cm = h.cost_model()
+    nx, nc, M = h.nreact_vars, h.ncomp, h.n_nodes - 1
+    per_iter = cm["residual_matrix"] + cm["lu"] + cm["solve"] + 2 * nx
+    per_solve = cm["source"] + 4 * nc
+    flops = stats["iters"] * per_iter + stats["solves"] * per_solve
+    Z = h.zones
+    words = {
+        "transition_first": 3 * nc + (nc + nx),
+        "transition_node0": (M + 1) * (nc + nx) + 2 * nc + (nc + nx) + (M - 1) * nc,
+        "transition_later": 4 * nc + (nc + nx),
+    }
+    bytes_ = sum(8.0 * Z * words[k] * nlaunch[k] for k in work_kinds)
+    return flops, bytes_, per_iter, per_solve
+
+
+def run_gpu(w, precision, steps, warmup):
+    import torch
+    from paper_1910_12578_amd import SDC, config_from_workload
+    cfg = config_from_workload(w, precision=precision)
+    h = SDC(cfg, w["network"])
+    nc = w["U0"].shape[0]
+    U = torch.from_numpy(w["U0"].reshape(nc, -1)).to("cuda")
+    work = h.alloc_nodes()
+    dt = w["dt"]
+    stream = torch.cuda.current_stream()
+    h.step(dt, warmup, U, work)
+    torch.cuda.synchronize()
+    h.stats_reset()
+    h.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.step(dt, steps, U, work, stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = h.profile_read()
+    h.profile(False)
+    st = h.stats()
+    ok = bool(torch.isfinite(U).all().item())
+    kinds = ("transition_first", "transition_node0", "transition_later")
+    nlaunch = {k: prof[k][1] for k in kinds}
+    t_trans = sum(prof[k][0] for k in kinds) * 1e-3
+    flops, bytes_, per_iter, per_solve = transition_model(h, kinds, st, nlaunch)
+    res = dict(
+        elapsed=elapsed, ms_per_step=1e3 * elapsed / steps, zone_updates=w["U0"][0].size * steps / elapsed,
+        stats=st, mean_newton=st["iters"] / max(st["solves"] - st["failed"], 1), finite=ok,
+        profile={k: dict(ms=round(v[0], 3), launches=v[1]) for k, v in prof.items() if v[1]},
+        transition=dict(seconds=t_trans, flops=flops, bytes=bytes_, flops_per_iter=per_iter,
+                        flops_per_solve=per_solve,
+                        avg_launch_ms=1e3 * t_trans / max(sum(nlaunch.values()), 1)),
+        cost_model=h.cost_model(),
+    )
+    h.close()
+    del U, work
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(w, edge):
+    """The oracle on an edge^3 corner of the same initial state, one step."""
+    from threadpoolctl import threadpool_limits
+    from oracle import sdc as osdc
+    dim = w["dim"]
+    sl = (slice(None),) + (slice(0, edge),) * dim
+    sub = dict(w, shape=(edge,) * dim)
+    U0 = np.ascontiguousarray(w["U0"][sl])
+    prob = osdc.Problem.from_workload(sub)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        osdc.run(U0, w["dt"], 1, prob)
+        t = time.perf_counter() - t0
+    return dict(value=U0[0].size / t, unit="zone-updates/s", cores=1, kind="oracle",
+                sample=f"one step of a {edge}^{dim} corner of the same initial state "
+                       f"({U0[0].size} zones, same dt, network and iteration counts), NumPy FP64, "
+                       f"single thread, {t:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="net3d")
+    ap.add_argument("--shape", default=None, help="override grid, e.g. 64,64,64")
+    ap.add_argument("--precision", default="both", choices=("fp64", "mixed", "both"))
+    ap.add_argument("--cpu-edge", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {a.gpus}); multi-GPU sharding is a design "
+              f"note, not a measured path", file=sys.stderr)
+        sys.exit(2)
+    shape = tuple(int(v) for v in a.shape.split(",")) if a.shape else None
+    print(f"[bench] generating {a.workload} {shape or ''}", file=sys.stderr, flush=True)
+    w = si.workload(a.workload, shape=shape)
+    Z = w["U0"][0].size
+    runs = {}
+    for name, prec in (("fp64", 0), ("mixed", 1)):
+        if a.precision in (name, "both"):
+            print(f"[bench] {name}: warmup {a.warmup}, timed {a.steps} steps", file=sys.stderr, flush=True)
+            runs[name] = run_gpu(w, prec, a.steps, a.warmup)
+            print(f"[bench] {name}: {runs[name]['zone_updates']:.4e} zone-updates/s", file=sys.stderr, flush=True)
+    head = runs.get("fp64") or runs["mixed"]
+    tr = head["transition"]
+    achieved = tr["flops"] / tr["seconds"] / 1e12 if tr["seconds"] > 0 else 0.0
+    out = dict(
+        metric="SDC zone-updates/s, 256^3 x 13 species (FP64; mixed beside it)",
+        value=head["zone_updates"],
+        unit="zone-updates/s",
+        n_gpus=1, steps=a.steps, warmup=a.warmup,
+        ms_per_step=head["ms_per_step"],
+        higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64" if "fp64" in runs else "f64+f32lu",
+        data="synthetic",
+        config=dict(workload=f"{a.workload} {'x'.join(map(str, w['shape']))}, {w['network']['nspec']} species / "
+                             f"{w['network']['nreact']} reactions, {w['n_nodes']} Gauss-Lobatto nodes, "
+                             f"K={w['n_iters']}", zones=Z, dt=w["dt"]),
+        roofline=dict(bound="alu", kernel="sdc_transition_* (fused quadrature + explicit update + Newton)",
+                      achieved=achieved, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                      frac=achieved / PEAK_FP64_TFLOPS, traffic=None,
+                      hbm_achieved_GBs=tr["bytes"] / tr["seconds"] / 1e9 if tr["seconds"] > 0 else 0.0,
+                      avg_launch_ms=tr["avg_launch_ms"]),
+        mean_newton_iterations=head["mean_newton"],
+        newton_failed=head["stats"]["failed"],
+        kernels_ms=head["profile"],
+    )
+    if "mixed" in runs and "fp64" in runs:
+        out["mixed"] = dict(value=runs["mixed"]["zone_updates"], ms_per_step=runs["mixed"]["ms_per_step"],
+                            speedup_vs_fp64=runs["mixed"]["zone_updates"] / runs["fp64"]["zone_updates"],
+                            mean_newton_iterations=runs["mixed"]["mean_newton"],
+                            kernels_ms=runs["mixed"]["profile"])
+    if not a.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_edge)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,238 @@
+/*
+ * sdc.h -- C ABI of the MI355X SDC reactive-flow library (libsdc.so).
+ *
+ * The library implements the hot path of the spectral deferred corrections
+ * (SDC) update of Zingale et al., "The Castro AMR Simulation Code: Current
+ * and Future Developments" (Sec. 2): the conservative split U_t = A(U) + R(U)
+ * (Eq. 1) and the node-to-node correction of Eq. 2,
+ *
+ *   U^{m+1,(k+1)} = U^{m,(k+1)} + dt_m [A^{m,(k+1)} - A^{m,(k)}]
+ *                 + dt_m [R^{m+1,(k+1)} - R^{m+1,(k)}]
+ *                 + int_{t^m}^{t^{m+1}} (A^{(k)} + R^{(k)}) dt,
+ *
+ * whose implicit reaction part is solved per zone by Newton with an analytic
+ * Jacobian.  Every computation runs in HIP kernels on the GPU.
+ *
+ * Conventions for every entry point:
+ *  - Floating-point arrays are float64, device memory, contiguous, in
+ *    structure-of-arrays layout [component][zone] with the zone index
+ *    x-fastest (z = i + n0*(j + n1*k)).  Base pointers must be 8-byte aligned
+ *    (256-byte alignment gives the best bandwidth).
+ *  - Full states U have n_c = 2 + dim + nspec components:
+ *      0: rho, 1..dim: rho u_d, dim+1: rho E, dim+2+s: rho X_s.
+ *    Reacting arrays (sources R, Newton vectors) have n_r = nspec + 1
+ *    components: (rho X_1 .. rho X_nspec, rho e); the last one acts on rho E.
+ *  - The caller owns every array passed in; the library never frees or
+ *    reallocates them.  The handle owns its own device buffers (network
+ *    parameters, statistics counters, cached graphs).
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL = the
+ *    default stream).  The return code reports argument validation and launch
+ *    errors only; device-side outcomes (unconverged or non-finite zones) are
+ *    read with sdc_stats, which synchronises.
+ *  - Functions never abort or throw across the ABI.  On failure they return a
+ *    nonzero SDC_ERR_* code and sdc_last_error describes it.
+ *  - A handle is not thread-safe and serves one stream at a time.
+ */
+#ifndef SDC_H
+#define SDC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SDC_OK 0
+#define SDC_ERR_ARG 1         /* invalid argument or configuration */
+#define SDC_ERR_HIP 2         /* a HIP runtime call failed */
+#define SDC_ERR_NOMEM 3       /* device allocation failed */
+#define SDC_ERR_NEWTON 4      /* reserved: some zones did not converge (see sdc_stats) */
+#define SDC_ERR_NONFINITE 5   /* reserved: non-finite results (see sdc_stats) */
+#define SDC_ERR_UNSUPPORTED 6 /* configuration outside the supported range */
+#define SDC_ERR_COMPILE 7     /* run-time compilation of the kernels failed */
+
+#define SDC_FP64 0  /* every step in float64 */
+#define SDC_MIXED 1 /* Newton matrix and LU in float32; residual, update, quadrature in float64 */
+
+#define SDC_MAX_NODES 5  /* Gauss-Lobatto nodes per step: 2..5 */
+#define SDC_MAX_SPECIES 31
+
+/* counters returned by sdc_stats */
+#define SDC_STAT_HIST 0       /* [0..15]: solves by Newton iteration count (15 = 15 or more) */
+#define SDC_STAT_FAILED 16    /* solves that did not converge within newton_maxiter */
+#define SDC_STAT_ITERS 17     /* total Newton iterations of converged solves */
+#define SDC_STAT_NONFINITE 18 /* solves whose result is not finite */
+#define SDC_STAT_SOLVES 19    /* zone solves */
+#define SDC_STAT_FALLBACK 20  /* Newton iterations that took the pivoted dense path */
+#define SDC_NSTATS 21
+
+typedef struct sdc_handle_s* sdc_handle;
+
+/*
+ * Reaction network (host memory, copied by sdc_init).  Synthetic Arrhenius
+ * kinetics on x = (rho X, rho e) with T = (gamma - 1) x_e / rho:
+ *   k_r = exp(lnA_r + b_r ln T - E_r / T)
+ *   v_r = k_r x_a (unimolecular)  or  k_r x_a x_c (bimolecular)
+ *   R_i = sum_r stoich[r][i] v_r,  R_e = sum_r Q_r v_r,  Q_r = -sum_i stoich[r][i] q_i.
+ * The paper's network is a stiff nuclear network (Sec. 2, Sec. 4); this one is
+ * drawn from a seed and carries no physical data.
+ */
+typedef struct {
+  int32_t nspec;             /* species, 1..SDC_MAX_SPECIES */
+  int32_t nreact;            /* reactions, >= 0 */
+  const int32_t* reactants;  /* [nreact][2] reactant species; second = -1 for unimolecular */
+  const double* stoich;      /* [nreact][nspec] stoichiometric coefficients (mass units) */
+  const double* lnA;         /* [nreact] */
+  const double* b;           /* [nreact] temperature exponents */
+  const double* E;           /* [nreact] activation temperatures */
+  const double* q;           /* [nspec] specific binding energies */
+} sdc_network;
+
+/* Grid, method and solver settings (host memory, copied by sdc_init). */
+typedef struct {
+  int32_t dim;             /* 1, 2 or 3 */
+  int64_t n[3];            /* zones per direction (x, y, z); entries beyond dim ignored */
+  double dx[3];            /* zone widths; the grid is periodic in every direction */
+  double gamma;            /* gamma-law EOS, p = (gamma - 1) rho e, code units p = rho T */
+  int32_t n_nodes;         /* Gauss-Lobatto nodes per step (2 = trapezoid, 3 = Simpson, .. 5) */
+  int32_t n_iters;         /* SDC iterations K per step, >= 1 */
+  int32_t precision;       /* SDC_FP64 or SDC_MIXED */
+  int32_t advection;       /* 0: A == 0 (reaction only), 1: advective term on */
+  int32_t slope;           /* 0: central slopes, 1: monotonized-central slopes */
+  double alpha;            /* > 0: frozen Rusanov speed; <= 0: local max(|u| + c) */
+  double newton_tol;       /* stop when max_i |delta_i| / s_i <= tol (s = rho, |b_e|) */
+  int32_t newton_maxiter;  /* >= 1 */
+  double pivot_threshold;  /* tau: a pivot below tau * column max takes the pivoted path */
+} sdc_config;
+
+/*
+ * Caller-owned node arrays for sdc_sweep / sdc_step, M = n_nodes - 1:
+ *   U[0..M]  [n_c][Z]  states at the nodes
+ *   A[0..M]  [n_c][Z]  advective terms at the nodes
+ *   R[0..M]  [n_r][Z]  reactive sources at the nodes
+ *   C[0..M-2][n_c][Z]  correction terms of transitions 1..M-1 (scratch)
+ * Unused entries may be NULL.  Distinct entries must not overlap.
+ */
+typedef struct {
+  double* U[SDC_MAX_NODES];
+  double* A[SDC_MAX_NODES];
+  double* R[SDC_MAX_NODES];
+  double* C[SDC_MAX_NODES - 2];
+} sdc_nodes;
+
+/* Fill `cfg` with defaults: 3 nodes, K = 4, FP64, MC slopes, local Rusanov
+ * speed, gamma 1.4, tol 1e-13, maxiter 50, pivot threshold 0.1. */
+int sdc_config_default(sdc_config* cfg);
+
+/*
+ * Create a handle: validates the configuration, generates the network's
+ * device code (rates, residual, packed Newton matrix and its fixed-order LU)
+ * and compiles it with the kernels for gfx950 (cached on disk, see
+ * SDC_KERNEL_CACHE), uploads the network parameters.
+ * Errors: SDC_ERR_ARG, SDC_ERR_UNSUPPORTED, SDC_ERR_COMPILE, SDC_ERR_HIP,
+ * SDC_ERR_NOMEM.  On error *out is NULL; sdc_last_error(NULL) explains.
+ */
+int sdc_init(const sdc_config* cfg, const sdc_network* net, sdc_handle* out);
+
+/* Release the handle and its device buffers (synchronises its work first). */
+int sdc_destroy(sdc_handle h);
+
+/* Description of the last error on `h` (or of the calling thread's last
+ * sdc_init failure when h is NULL).  Owned by the library. */
+const char* sdc_last_error(sdc_handle h);
+
+/* Zones Z, components n_c and reacting components n_r of the handle's grid. */
+int sdc_sizes(sdc_handle h, int64_t* zones, int32_t* ncomp, int32_t* nreact_vars);
+
+/*
+ * A = <A(U)>: the advective term of Eq. 1 on the periodic grid, the negative
+ * divergence of Rusanov fluxes of a piecewise-linear reconstruction of the
+ * conserved variables (method of lines).  U, A: [n_c][Z]; must not overlap.
+ */
+int sdc_advective_term(sdc_handle h, const double* U, double* A, void* stream);
+
+/* R = R(U): the reactive source of Eq. 1 on the reacting components,
+ * evaluated at x = (rho X, rho E - |rho u|^2 / (2 rho)).  U: [n_c][Z], R: [n_r][Z]. */
+int sdc_source(sdc_handle h, const double* U, double* R, void* stream);
+
+/*
+ * The implicit part of Eq. 2 alone, per zone: solve x - dt_m R(x; rho) = b by
+ * Newton from the guess in x.  rho: [Z]; b, x, R: [n_r][Z]; iters: int32 [Z].
+ * Outputs: x = root, R = R(x), iters = Newton iterations or -1 (not converged
+ * within newton_maxiter; x keeps the last iterate).  x and b must not overlap.
+ */
+int sdc_reaction_solve(sdc_handle h, double dt_m, const double* rho, const double* b, double* x,
+                       double* R, int32_t* iters, void* stream);
+
+/*
+ * One SDC iteration k -> k+1 over the transitions m = 0..M-1 of Eq. 2 for a
+ * step of length dt, followed by A at the last node.  On entry nodes->U[0],
+ * A[0], R[0] hold U^n, A(U^n), R(U^n); for k >= 1 the other nodes hold
+ * iteration k; for k == 0 every iteration-0 node is taken to equal node 0
+ * (entries 1..M are not read).  On return nodes 1..M hold iteration k+1.
+ */
+int sdc_sweep(sdc_handle h, double dt, int32_t k, const sdc_nodes* nodes, void* stream);
+
+/*
+ * nsteps SDC steps of length dt, each of n_iters sweeps; U [n_c][Z] holds
+ * U^n on entry and the final state on return (U^{n+1} = U^{M,(K)}).  `work`
+ * supplies the node arrays (U, A, R for every node and C when M >= 2); none
+ * of them may overlap U.  The last node's A and R carry over as node 0 of the
+ * next step.
+ */
+int sdc_step(sdc_handle h, double dt, int32_t nsteps, double* U, const sdc_nodes* work, void* stream);
+
+/* Copy the accumulated counters (SDC_STAT_*) to host `out[SDC_NSTATS]`;
+ * synchronises the handle's last stream. */
+int sdc_stats(sdc_handle h, int64_t* out);
+
+/* Zero the counters (enqueued on `stream`). */
+int sdc_stats_reset(sdc_handle h, void* stream);
+
+/* Replace the rate parameters lnA and E (host arrays [nreact]); enqueued on
+ * the handle's last stream before any later work. */
+int sdc_set_params(sdc_handle h, const double* lnA, const double* E);
+
+/* Kernel kinds for sdc_profile_read. */
+#define SDC_K_ADVECT 0
+#define SDC_K_SOURCE 1
+#define SDC_K_SOLVE 2
+#define SDC_K_TRANSITION_FIRST 3
+#define SDC_K_TRANSITION_NODE0 4
+#define SDC_K_TRANSITION_LATER 5
+#define SDC_K_FILL 6
+#define SDC_NKINDS 7
+
+/*
+ * Per-kernel timing: while enabled, every launch is bracketed by HIP events
+ * recorded on the launch stream.  sdc_profile_read synchronises, returns the
+ * summed milliseconds and launch counts per kernel kind (SDC_K_*; arrays of
+ * SDC_NKINDS) since the last read, and clears them.
+ */
+int sdc_profile_enable(sdc_handle h, int32_t enable);
+int sdc_profile_read(sdc_handle h, double* ms, int64_t* launches);
+
+/*
+ * Operation counts of the generated network code (add, mul, div, exp and log
+ * count 1, fused multiply-add 2): out[0] R(x), out[1] residual and Newton
+ * matrix, out[2] LU factorisation, out[3] triangular solves, out[4] exp calls
+ * per evaluation, out[5] structural nonzeros of the Newton matrix, out[6]
+ * with fill-in.
+ */
+int sdc_cost_model(sdc_handle h, int64_t* out);
+
+/*
+ * Compile (or find in the cache) the kernels for `cfg` and `net` without
+ * touching a GPU; for build steps that warm the kernel cache.
+ */
+int sdc_compile_only(const sdc_config* cfg, const sdc_network* net);
+
+/* Generated device source for `cfg` and `net` (for inspection): copies up to
+ * `len` bytes including the terminator into `buf` and returns the full length
+ * needed, or a negative SDC_ERR_* code. */
+int64_t sdc_generated_source(const sdc_config* cfg, const sdc_network* net, char* buf, int64_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SDC_H */

@@ -1,0 +1,75 @@
+// Kernel argument blocks shared by the host runtime and the HIP kernels.
+// Plain C structs passed by value; pointers are device addresses.
+#ifndef SDC_ARGS_H
+#define SDC_ARGS_H
+
+typedef long long sdc_i64;
+#define SDC_MAXNODE 5
+
+typedef struct {
+  double tol;   // Newton stopping tolerance
+  double tau;   // pivot threshold of the fixed-order LU
+  int maxiter;
+} NewtonCtl;
+
+typedef struct {
+  const double* U;
+  double* A;
+  sdc_i64 Z;
+  int n[3];
+  double idx[3];  // 1 / dx_d
+  double gamma;
+  double alpha;   // > 0: frozen Rusanov speed
+  int slope;      // 0 = central, 1 = MC
+} AdvArgs;
+
+typedef struct {
+  sdc_i64 Z;
+  double dtm;
+  const double* rho;
+  const double* b;
+  double* x;
+  double* R;
+  int* iters;
+  const void* P;  // NetParams in device memory
+  double gm1;
+  NewtonCtl ctl;
+  unsigned long long* stats;
+} SolveArgs;
+
+typedef struct {
+  sdc_i64 Z;
+  const double* U;
+  double* R;
+  const void* P;
+  double gm1;
+} SourceArgs;
+
+typedef struct {
+  sdc_i64 Z;
+  int m, M, first;
+  double dt, dtm;
+  double S[SDC_MAXNODE - 1][SDC_MAXNODE];  // unit-interval integration matrix
+  double dtj[SDC_MAXNODE - 1];             // dt_j = (tau_{j+1} - tau_j) dt
+  const double* Um;                        // U^{m,(k+1)} (U^n for m = 0)
+  const double* Am;                        // A^{m,(k+1)}
+  const double* Aold[SDC_MAXNODE];         // A^{j,(k)}     (m = 0, k >= 1)
+  const double* Rold[SDC_MAXNODE];         // R^{j,(k)}     (m = 0, k >= 1)
+  const double* Cin;                       // C_m           (m >= 1, k >= 1)
+  double* Cout[SDC_MAXNODE - 2];           // C_1..C_{M-1}  (m = 0, k >= 1)
+  const double* guess;                     // U^{m+1,(k)}, or U^n at k = 0
+  double* Uout;
+  double* Rout;
+  const void* P;
+  double gm1;
+  NewtonCtl ctl;
+  unsigned long long* stats;
+} TransArgs;
+
+typedef struct {
+  double* p;
+  sdc_i64 n;
+  double v;
+} FillArgs;
+
+#endif

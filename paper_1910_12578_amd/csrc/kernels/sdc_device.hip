@@ -1,0 +1,531 @@
+// Hand-written HIP kernels of the SDC reactive-flow update for gfx950.
+//
+// This source is compiled at sdc_init together with the network code that
+// netgen.cpp generates for the caller's reaction network (it defines SDC_NS,
+// SDC_NR, SDC_NX, SDC_NNZ, NetParams and the net_* functions) and with
+// SDC_DIM.  Every kernel works on structure-of-arrays state, U[comp][zone]
+// with the zone index x-fastest; the components are
+//   0: rho,  1..DIM: rho u_d,  DIM+1: rho E,  DIM+2+s: rho X_s,
+// and reacting-variable arrays (sources R, Newton vectors) are [NX][zone]
+// with x = (rho X_1..rho X_Ns, rho e).
+//
+// Paper: Zingale et al., Castro, Sec. 2.  Eq. 1 splits U_t = A(U) + R(U);
+// Eq. 2 is the node-to-node SDC correction, whose implicit part
+// U^{m+1} - dt_m R(U^{m+1}) = rhs is solved here per zone by Newton.
+#ifndef __HIPCC_RTC__
+#include <hip/hip_runtime.h>
+#endif
+
+#include "sdc_args.h"
+
+#ifndef SDC_DIM
+#error "SDC_DIM must be defined"
+#endif
+#define SDC_NC (2 + SDC_DIM + SDC_NS)
+#define SDC_NH (2 + SDC_DIM)
+
+typedef long long i64;
+typedef unsigned long long u64;
+
+// ------------------------------------------------------------------ launch
+// Blocks are dealt round-robin to the 8 XCDs; remap so that each XCD works on
+// a contiguous range of zones and neighbouring stencil blocks share its L2.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+  const unsigned nx = 8u;
+  const unsigned per = nb / nx, rem = nb % nx;
+  const unsigned x = b % nx, i = b / nx;
+  return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + i;
+}
+
+// ------------------------------------------------------------ statistics
+// counters: [0..15] histogram of Newton iterations (bin 15 = 15 or more),
+// [16] failed solves, [17] total Newton iterations, [18] non-finite results,
+// [19] solves, [20] pivot fallbacks.
+#define SDC_NSTAT 21
+__device__ __forceinline__ void stats_block(unsigned long long* __restrict__ stats, int nu, bool valid, bool nonfinite, int fallbacks) {
+  __shared__ unsigned sh[SDC_NSTAT];
+  if (threadIdx.x < SDC_NSTAT) sh[threadIdx.x] = 0u;
+  __syncthreads();
+  if (valid) {
+    if (nu > 0) {
+      atomicAdd(&sh[nu < 15 ? nu : 15], 1u);
+      atomicAdd(&sh[17], (unsigned)nu);
+    } else {
+      atomicAdd(&sh[16], 1u);
+    }
+    if (nonfinite) atomicAdd(&sh[18], 1u);
+    atomicAdd(&sh[19], 1u);
+    if (fallbacks) atomicAdd(&sh[20], (unsigned)fallbacks);
+  }
+  __syncthreads();
+  if (threadIdx.x < SDC_NSTAT && sh[threadIdx.x] != 0u) atomicAdd(&stats[threadIdx.x], (u64)sh[threadIdx.x]);
+}
+
+// ------------------------------------------------------------ advection
+// A(U) = -sum_d (F_{i+1/2} - F_{i-1/2}) / dx_d: method of lines, piecewise-
+// linear reconstruction of the conserved variables (central or monotonized-
+// central slopes), Rusanov face flux with the local max(|u_d| + c) of the two
+// face states or a frozen speed, periodic grid.
+
+__device__ __forceinline__ double slope_of(double um, double u0, double up, int slope) {
+  if (slope == 0) return 0.5 * (up - um);
+  const double a = u0 - um, b = up - u0;
+  if (!(a * b > 0.0)) return 0.0;
+  const double m = fmin(fmin(2.0 * fabs(a), 2.0 * fabs(b)), 0.5 * fabs(a + b));
+  return a > 0.0 ? m : -m;
+}
+
+// Face state pair (left/right of one face) of the hydro components.
+struct FaceHydro {
+  double uL, uR, a;  // normal velocities, Rusanov speed
+};
+
+__device__ __forceinline__ void hydro_flux(const double* W, int d, double gamma, double* F, double& un, double& p, double& c) {
+  const double rho = W[0];
+  const double ir = 1.0 / rho;
+  double ke = 0.0;
+#pragma unroll
+  for (int e = 0; e < SDC_DIM; ++e) ke = fma(W[1 + e], W[1 + e], ke);
+  ke = 0.5 * ke * ir;
+  un = W[1 + d] * ir;
+  p = (gamma - 1.0) * (W[1 + SDC_DIM] - ke);
+  c = sqrt(gamma * p * ir);
+#pragma unroll
+  for (int q = 0; q < SDC_NH; ++q) F[q] = W[q] * un;
+  F[1 + d] += p;
+  F[1 + SDC_DIM] += p * un;
+}
+
+extern "C" __global__ __launch_bounds__(256) void sdc_advect(AdvArgs a) {
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  const i64 z = (i64)b * blockDim.x + threadIdx.x;
+  if (z >= a.Z) return;
+  int c3[3] = {0, 0, 0};
+  {
+    i64 t = z;
+    c3[0] = (int)(t % a.n[0]);
+    t /= a.n[0];
+    if (SDC_DIM > 1) {
+      c3[1] = (int)(t % a.n[1]);
+      t /= a.n[1];
+    }
+    if (SDC_DIM > 2) c3[2] = (int)t;
+  }
+  const double* __restrict__ U = a.U;
+  // periodic neighbour offsets i-2..i+2 (without the centre) per direction
+  i64 off[SDC_DIM][4];
+  {
+    i64 stride = 1;
+#pragma unroll
+    for (int d = 0; d < SDC_DIM; ++d) {
+      const int nd = a.n[d], cd = c3[d];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int sh = s < 2 ? s - 2 : s - 1;
+        int cc = cd + sh;
+        cc = cc < 0 ? cc + nd : (cc >= nd ? cc - nd : cc);
+        off[d][s] = (i64)(cc - cd) * stride;
+      }
+      stride *= nd;
+    }
+  }
+  // ---- hydro components, face velocities and speeds per direction
+  FaceHydro fh[SDC_DIM][2];
+  double acc[SDC_NH];
+#pragma unroll
+  for (int q = 0; q < SDC_NH; ++q) acc[q] = 0.0;
+#pragma unroll
+  for (int d = 0; d < SDC_DIM; ++d) {
+    double WL[2][SDC_NH], WR[2][SDC_NH];  // face 0 = i-1/2, face 1 = i+1/2
+#pragma unroll
+    for (int q = 0; q < SDC_NH; ++q) {
+      const double* Uq = U + (i64)q * a.Z + z;
+      const double h0 = Uq[off[d][0]], h1 = Uq[off[d][1]], h2 = Uq[0], h3 = Uq[off[d][2]], h4 = Uq[off[d][3]];
+      const double sm = slope_of(h0, h1, h2, a.slope);
+      const double s0 = slope_of(h1, h2, h3, a.slope);
+      const double sp = slope_of(h2, h3, h4, a.slope);
+      WL[0][q] = h1 + 0.5 * sm;
+      WR[0][q] = h2 - 0.5 * s0;
+      WL[1][q] = h2 + 0.5 * s0;
+      WR[1][q] = h3 - 0.5 * sp;
+    }
+    double Fh[2][SDC_NH];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      double FL[SDC_NH], FR[SDC_NH], pL, pR, cL, cR;
+      hydro_flux(WL[f], d, a.gamma, FL, fh[d][f].uL, pL, cL);
+      hydro_flux(WR[f], d, a.gamma, FR, fh[d][f].uR, pR, cR);
+      fh[d][f].a = a.alpha > 0.0 ? a.alpha : fmax(fabs(fh[d][f].uL) + cL, fabs(fh[d][f].uR) + cR);
+#pragma unroll
+      for (int q = 0; q < SDC_NH; ++q) Fh[f][q] = 0.5 * (FL[q] + FR[q]) - 0.5 * fh[d][f].a * (WR[f][q] - WL[f][q]);
+    }
+    const double id = a.idx[d];
+#pragma unroll
+    for (int q = 0; q < SDC_NH; ++q) acc[q] -= (Fh[1][q] - Fh[0][q]) * id;
+  }
+#pragma unroll
+  for (int q = 0; q < SDC_NH; ++q) a.A[(i64)q * a.Z + z] = acc[q];
+  // ---- passive species, one at a time, with the hydro faces' u and speed
+#pragma unroll 1
+  for (int s = 0; s < SDC_NS; ++s) {
+    const double* Us = U + (i64)(SDC_NH + s) * a.Z + z;
+    const double v2 = Us[0];
+    double A = 0.0;
+#pragma unroll
+    for (int d = 0; d < SDC_DIM; ++d) {
+      const double v0 = Us[off[d][0]], v1 = Us[off[d][1]], v3 = Us[off[d][2]], v4 = Us[off[d][3]];
+      const double sm = slope_of(v0, v1, v2, a.slope);
+      const double s0 = slope_of(v1, v2, v3, a.slope);
+      const double sp = slope_of(v2, v3, v4, a.slope);
+      double F0, F1;
+      {
+        const double L = v1 + 0.5 * sm, R = v2 - 0.5 * s0;
+        F0 = 0.5 * (L * fh[d][0].uL + R * fh[d][0].uR) - 0.5 * fh[d][0].a * (R - L);
+      }
+      {
+        const double L = v2 + 0.5 * s0, R = v3 - 0.5 * sp;
+        F1 = 0.5 * (L * fh[d][1].uL + R * fh[d][1].uR) - 0.5 * fh[d][1].a * (R - L);
+      }
+      A -= (F1 - F0) * a.idx[d];
+    }
+    a.A[(i64)(SDC_NH + s) * a.Z + z] = A;
+  }
+}
+
+// ------------------------------------------------------------ reactions
+struct VecX {
+  double v[SDC_NX];
+};
+
+struct DenseResult {
+  VecX x;
+  int it;  // iteration count at exit, or -1
+};
+
+// Newton with a dense, partially pivoted LU of M = I - dt_m dR/dx, continued
+// from iterate x after `it0` iterations.  Used only for zones whose fixed-
+// order factorisation met a pivot below tau times its column maximum.  It is
+// kept out of line and written with rolled loops over the topology tables, so
+// that its arrays live in scratch memory and the fast path's register budget
+// does not pay for it.
+__device__ __attribute__((noinline)) DenseResult dense_newton(VecX xv, VecX bv, double rho, double dtm, ParamPtr P,
+                                                              double gm1, double tol, int it0, int maxiter) {
+  DenseResult out;
+  double x[SDC_NX], b[SDC_NX];
+  for (int i = 0; i < SDC_NX; ++i) {
+    x[i] = xv.v[i];
+    b[i] = bv.v[i];
+  }
+  const double irho = 1.0 / rho;
+  const double ise = 1.0 / fabs(b[SDC_NX - 1]);
+  const int e = SDC_NX - 1;
+  out.it = -1;
+  for (int it = it0; it <= maxiter; ++it) {
+    double M[SDC_NX * SDC_NX];
+    double r[SDC_NX];
+    for (int i = 0; i < SDC_NX * SDC_NX; ++i) M[i] = 0.0;
+    for (int i = 0; i < SDC_NX; ++i) {
+      M[i * SDC_NX + i] = 1.0;
+      r[i] = b[i] - x[i];  // -G without the reaction terms
+    }
+    const double T = gm1 * x[e] * irho, lnT = log(T), invT = 1.0 / T, dTdxe = gm1 * irho;
+    for (int q = 0; q < SDC_NR; ++q) {
+      const double k = exp(fma(P->b[q], lnT, P->lnA[q]) - P->E[q] * invT);
+      const int a = kRxA[q], c = kRxC[q];
+      const double mono = c < 0 ? x[a] : x[a] * x[c];
+      const double v = k * mono;
+      const double da = c < 0 ? k : (a == c ? 2.0 * k * x[a] : k * x[c]);
+      const double dc = c < 0 ? 0.0 : (a == c ? 0.0 : k * x[a]);
+      const double de = v * fma(P->E[q], invT * invT, P->b[q] * invT) * dTdxe;
+      for (int s = 0; s <= kRxN[q]; ++s) {
+        const int i = s < kRxN[q] ? kRxSp[q][s] : e;
+        const double w = (s < kRxN[q] ? kRxS[q][s] : P->Q[q]) * dtm;  // row weight
+        r[i] = fma(w, v, r[i]);
+        M[i * SDC_NX + a] -= w * da;
+        if (c >= 0) M[i * SDC_NX + c] -= w * dc;
+        M[i * SDC_NX + e] -= w * de;
+      }
+    }
+    for (int k = 0; k < SDC_NX; ++k) {
+      int p = k;
+      double best = fabs(M[k * SDC_NX + k]);
+      for (int i = k + 1; i < SDC_NX; ++i) {
+        const double v = fabs(M[i * SDC_NX + k]);
+        if (v > best) {
+          best = v;
+          p = i;
+        }
+      }
+      if (p != k) {
+        for (int j = k; j < SDC_NX; ++j) {
+          const double t = M[k * SDC_NX + j];
+          M[k * SDC_NX + j] = M[p * SDC_NX + j];
+          M[p * SDC_NX + j] = t;
+        }
+        const double t = r[k];
+        r[k] = r[p];
+        r[p] = t;
+      }
+      const double inv = 1.0 / M[k * SDC_NX + k];
+      for (int i = k + 1; i < SDC_NX; ++i) {
+        const double l = M[i * SDC_NX + k] * inv;
+        for (int j = k + 1; j < SDC_NX; ++j) M[i * SDC_NX + j] = fma(-l, M[k * SDC_NX + j], M[i * SDC_NX + j]);
+        r[i] = fma(-l, r[k], r[i]);
+      }
+    }
+    double err = 0.0, inf_or_nan = ise * 0.0;
+    for (int k = SDC_NX - 1; k >= 0; --k) {
+      double s = r[k];
+      for (int j = k + 1; j < SDC_NX; ++j) s = fma(-M[k * SDC_NX + j], r[j], s);
+      r[k] = s / M[k * SDC_NX + k];
+      x[k] += r[k];
+      err = fmax(err, fabs(r[k]) * (k == e ? ise : irho));
+      inf_or_nan += r[k] * 0.0;
+    }
+    if (!(inf_or_nan == 0.0)) break;
+    if (err <= tol) {
+      out.it = it;
+      break;
+    }
+  }
+  for (int i = 0; i < SDC_NX; ++i) out.x.v[i] = x[i];
+  return out;
+}
+
+// Solve x - dt_m R(x; rho) = b by Newton from the guess in x.  Stops when
+// max_i |delta_i| / s_i <= tol (s = rho for species, |b_e| for energy), after
+// at least one iteration; returns the iteration count or -1.  MT is the type
+// of the Newton matrix and its LU factors (double, or float for the mixed
+// mode where the residual and the update stay in double).
+template <class MT>
+__device__ __forceinline__ int newton_solve(double* x, const double* b, double rho, double dtm, ParamPtr P,
+                                            double gm1, const NewtonCtl& ctl, int& fallbacks) {
+  const double irho = 1.0 / rho;
+  const double ise = 1.0 / fabs(b[SDC_NX - 1]);
+  int it = 1;
+  for (; it <= ctl.maxiter; ++it) {
+    double G[SDC_NX];
+    MT M[SDC_NNZ];
+    net_residual_matrix<MT>(x, b, irho, dtm, P, gm1, G, M);
+    if (!net_lu<MT>(M, (MT)ctl.tau)) break;  // pivot guard: finish on the dense path
+    MT r[SDC_NX];
+#pragma unroll
+    for (int i = 0; i < SDC_NX; ++i) r[i] = (MT)(-G[i]);
+    net_solve<MT>(M, r);
+    double err = 0.0, inf_or_nan = ise * 0.0;  // fmax drops NaN, so track it apart
+#pragma unroll
+    for (int i = 0; i < SDC_NX; ++i) {
+      const double d = (double)r[i];
+      x[i] += d;
+      err = fmax(err, fabs(d) * (i == SDC_NX - 1 ? ise : irho));
+      inf_or_nan += d * 0.0;
+    }
+    if (!(inf_or_nan == 0.0)) return -1;  // a non-finite step never converges
+    if (err <= ctl.tol) return it;
+  }
+  if (it > ctl.maxiter) return -1;
+  fallbacks = 1;
+  VecX xv, bv;
+#pragma unroll
+  for (int i = 0; i < SDC_NX; ++i) {
+    xv.v[i] = x[i];
+    bv.v[i] = b[i];
+  }
+  const DenseResult r = dense_newton(xv, bv, rho, dtm, P, gm1, ctl.tol, it, ctl.maxiter);
+#pragma unroll
+  for (int i = 0; i < SDC_NX; ++i) x[i] = r.x.v[i];
+  return r.it;
+}
+
+__device__ __forceinline__ bool all_finite(const double* x) {
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < SDC_NX; ++i) ok = ok && (fabs(x[i]) <= 1.7976931348623157e308);
+  return ok;
+}
+
+
+// ---- sdc_reaction_solve: the implicit part of Eq. 2 alone.
+template <class MT>
+__device__ __forceinline__ void reaction_solve_body(const SolveArgs& a) {
+  const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = z < a.Z;
+  int nu = 0, fb = 0;
+  bool nonfinite = false;
+  if (valid) {
+    double x[SDC_NX], b[SDC_NX];
+#pragma unroll
+    for (int i = 0; i < SDC_NX; ++i) {
+      x[i] = a.x[(i64)i * a.Z + z];
+      b[i] = a.b[(i64)i * a.Z + z];
+    }
+    const double rho = a.rho[z];
+    nu = newton_solve<MT>(x, b, rho, a.dtm, (ParamPtr)a.P, a.gm1, a.ctl, fb);
+    double R[SDC_NX];
+    net_source(x, 1.0 / rho, (ParamPtr)a.P, a.gm1, R);
+#pragma unroll
+    for (int i = 0; i < SDC_NX; ++i) {
+      a.x[(i64)i * a.Z + z] = x[i];
+      a.R[(i64)i * a.Z + z] = R[i];
+    }
+    a.iters[z] = nu;
+    nonfinite = !all_finite(x);
+  }
+  stats_block(a.stats, nu, valid, nonfinite, fb);
+}
+
+#ifndef SDC_MIXED
+extern "C" __global__ __launch_bounds__(256) void sdc_reaction_solve(SolveArgs a) { reaction_solve_body<double>(a); }
+#else
+extern "C" __global__ __launch_bounds__(256) void sdc_reaction_solve(SolveArgs a) { reaction_solve_body<float>(a); }
+#endif
+
+// ---- R(U): the reactive source of a full state, on the reacting variables.
+
+extern "C" __global__ __launch_bounds__(256) void sdc_source(SourceArgs a) {
+  const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= a.Z) return;
+  const double rho = a.U[z];
+  double ke = 0.0;
+#pragma unroll
+  for (int d = 0; d < SDC_DIM; ++d) {
+    const double m = a.U[(i64)(1 + d) * a.Z + z];
+    ke = fma(m, m, ke);
+  }
+  ke = 0.5 * ke / rho;
+  double x[SDC_NX], R[SDC_NX];
+#pragma unroll
+  for (int s = 0; s < SDC_NS; ++s) x[s] = a.U[(i64)(SDC_NH + s) * a.Z + z];
+  x[SDC_NX - 1] = a.U[(i64)(1 + SDC_DIM) * a.Z + z] - ke;
+  net_source(x, 1.0 / rho, (ParamPtr)a.P, a.gm1, R);
+#pragma unroll
+  for (int i = 0; i < SDC_NX; ++i) a.R[(i64)i * a.Z + z] = R[i];
+}
+
+// ------------------------------------------------------------ transition
+// One node transition m -> m+1 of Eq. 2 for every zone, fused:
+//   rhs = U^{m,(k+1)} + dt_m A^{m,(k+1)} + C_m,
+//   C_m = dt sum_j S_mj (A^{j,(k)} + R^{j,(k)}) - dt_m A^{m,(k)} - dt_m R^{m+1,(k)}
+// with C_m = 0 on the first sweep (every iteration-0 node holds U^n), and for
+// m = 0 the A^0 terms cancelling exactly.  rho and rho u are final after the
+// explicit part; (rho X, rho e) solve x - dt_m R(x) = b by Newton from the
+// previous iterate of node m+1; R^{m+1} is re-evaluated at the root.  The
+// m = 0 transition also forms C_1..C_{M-1} for the later transitions, before
+// anything of iteration k is overwritten.
+#ifndef SDC_NNODES
+#error "SDC_NNODES (number of Gauss-Lobatto nodes) must be defined"
+#endif
+#define SDC_M (SDC_NNODES - 1)
+enum { KIND_FIRST = 0, KIND_NODE0 = 1, KIND_LATER = 2 };
+
+// component c of the full state -> reacting index, or -1
+__device__ __forceinline__ constexpr int react_index(int c) {
+  return c == 1 + SDC_DIM ? SDC_NX - 1 : (c >= SDC_NH ? c - SDC_NH : -1);
+}
+
+// rhs[c] = v for a run-time c without dynamic register indexing
+__device__ __forceinline__ void rhs_store(double* rhs, int c, double v) {
+#pragma unroll
+  for (int q = 0; q < SDC_NC; ++q)
+    if (q == c) rhs[q] = v;
+}
+
+template <class MT, int KIND>
+__device__ __forceinline__ void transition_body(const TransArgs& a) {
+  const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = z < a.Z;
+  int nu = 0, fb = 0;
+  bool nonfinite = false;
+  if (valid) {
+    const i64 Z = a.Z;
+    double rhs[SDC_NC];
+    if (KIND == KIND_FIRST) {
+#pragma unroll
+      for (int c = 0; c < SDC_NC; ++c) rhs[c] = fma(a.dtm, a.Am[(i64)c * Z + z], a.Um[(i64)c * Z + z]);
+    } else if (KIND == KIND_NODE0) {
+#pragma unroll 1
+      for (int c = 0; c < SDC_NC; ++c) {
+        const int ri = c == 1 + SDC_DIM ? SDC_NX - 1 : (c >= SDC_NH ? c - SDC_NH : -1);
+        double f[SDC_NNODES];
+#pragma unroll
+        for (int j = 0; j <= SDC_M; ++j) {
+          f[j] = a.Aold[j][(i64)c * Z + z];
+          if (ri >= 0) f[j] += a.Rold[j][(i64)ri * Z + z];
+        }
+        double i0 = 0.0;
+#pragma unroll
+        for (int j = 0; j <= SDC_M; ++j) i0 = fma(a.S[0][j], f[j], i0);
+        double r = fma(a.dt, i0, a.Um[(i64)c * Z + z]);
+        if (ri >= 0) r = fma(-a.dtm, a.Rold[1][(i64)ri * Z + z], r);
+        rhs_store(rhs, c, r);
+#pragma unroll
+        for (int mm = 1; mm < SDC_M; ++mm) {
+          double im = 0.0;
+#pragma unroll
+          for (int j = 0; j <= SDC_M; ++j) im = fma(a.S[mm][j], f[j], im);
+          double cm = fma(-a.dtj[mm], a.Aold[mm][(i64)c * Z + z], a.dt * im);
+          if (ri >= 0) cm = fma(-a.dtj[mm], a.Rold[mm + 1][(i64)ri * Z + z], cm);
+          a.Cout[mm - 1][(i64)c * Z + z] = cm;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < SDC_NC; ++c)
+        rhs[c] = fma(a.dtm, a.Am[(i64)c * Z + z], a.Um[(i64)c * Z + z]) + a.Cin[(i64)c * Z + z];
+    }
+    // explicit part: rho and rho u are final
+    const double rho = rhs[0];
+    double ke = 0.0;
+#pragma unroll
+    for (int d = 0; d < SDC_DIM; ++d) ke = fma(rhs[1 + d], rhs[1 + d], ke);
+    ke = 0.5 * ke / rho;
+    double b[SDC_NX], x[SDC_NX];
+#pragma unroll
+    for (int s = 0; s < SDC_NS; ++s) b[s] = rhs[SDC_NH + s];
+    b[SDC_NX - 1] = rhs[1 + SDC_DIM] - ke;
+    // Newton guess: reacting vector of the previous iterate of node m+1
+    {
+      const double* __restrict__ g = a.guess;
+      const double grho = g[z];
+      double gke = 0.0;
+#pragma unroll
+      for (int d = 0; d < SDC_DIM; ++d) {
+        const double mo = g[(i64)(1 + d) * Z + z];
+        gke = fma(mo, mo, gke);
+      }
+      gke = 0.5 * gke / grho;
+#pragma unroll
+      for (int s = 0; s < SDC_NS; ++s) x[s] = g[(i64)(SDC_NH + s) * Z + z];
+      x[SDC_NX - 1] = g[(i64)(1 + SDC_DIM) * Z + z] - gke;
+    }
+    nu = newton_solve<MT>(x, b, rho, a.dtm, (ParamPtr)a.P, a.gm1, a.ctl, fb);
+    double R[SDC_NX];
+    net_source(x, 1.0 / rho, (ParamPtr)a.P, a.gm1, R);
+    double* __restrict__ Uo = a.Uout;
+    Uo[z] = rho;
+#pragma unroll
+    for (int d = 0; d < SDC_DIM; ++d) Uo[(i64)(1 + d) * Z + z] = rhs[1 + d];
+    Uo[(i64)(1 + SDC_DIM) * Z + z] = x[SDC_NX - 1] + ke;
+#pragma unroll
+    for (int s = 0; s < SDC_NS; ++s) Uo[(i64)(SDC_NH + s) * Z + z] = x[s];
+#pragma unroll
+    for (int i = 0; i < SDC_NX; ++i) a.Rout[(i64)i * Z + z] = R[i];
+    nonfinite = !all_finite(x);
+  }
+  stats_block(a.stats, nu, valid, nonfinite, fb);
+}
+
+#ifndef SDC_MIXED
+typedef double SdcMT;
+#else
+typedef float SdcMT;
+#endif
+extern "C" __global__ __launch_bounds__(256) void sdc_transition_first(TransArgs a) { transition_body<SdcMT, KIND_FIRST>(a); }
+extern "C" __global__ __launch_bounds__(256) void sdc_transition_node0(TransArgs a) { transition_body<SdcMT, KIND_NODE0>(a); }
+extern "C" __global__ __launch_bounds__(256) void sdc_transition_later(TransArgs a) { transition_body<SdcMT, KIND_LATER>(a); }
+
+// ---- constant fill (used instead of memset so that captured graphs stay valid)
+extern "C" __global__ __launch_bounds__(256) void sdc_fill(FillArgs a) {
+  const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < a.n) a.p[i] = a.v;
+}

@@ -1,0 +1,781 @@
+// Host runtime of libsdc.so: the C ABI declared in include/sdc.h.
+//
+// sdc_init validates the configuration, generates the network's device code
+// (netgen.cpp), compiles it together with the hand-written kernels
+// (kernels/sdc_device.hip) for gfx950 through hipRTC, caches the code object
+// on disk and loads it.  The entry points then only marshal arguments and
+// enqueue kernels: every arithmetic step of the SDC update runs on the GPU.
+#include <dlfcn.h>
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+#include <sys/stat.h>
+#include <unistd.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/sdc.h"
+#include "kernels/sdc_args.h"
+#include "netgen.hpp"
+
+// kSdcArgsSrc, kSdcDeviceSrc: the kernel sources as string literals
+#include "_gen/sdc_device_src.inc"
+
+namespace {
+
+thread_local std::string g_init_error;
+
+constexpr int kBlock = 256;
+
+// ------------------------------------------------------------ quadrature
+// Gauss-Lobatto points on [0, 1] for 2..5 nodes (closed forms).
+std::vector<double> lobatto_nodes(int n) {
+  switch (n) {
+    case 2: return {0.0, 1.0};
+    case 3: return {0.0, 0.5, 1.0};
+    case 4: {
+      const double a = 0.5 / std::sqrt(5.0);
+      return {0.0, 0.5 - a, 0.5 + a, 1.0};
+    }
+    case 5: {
+      const double a = 0.5 * std::sqrt(3.0 / 7.0);
+      return {0.0, 0.5 - a, 0.5, 0.5 + a, 1.0};
+    }
+  }
+  return {};
+}
+
+// S[m][j] = integral over [tau_m, tau_{m+1}] of the Lagrange polynomial l_j
+// through all nodes: the node-to-node quadrature of the integral in Eq. 2.
+std::vector<std::vector<double>> integration_matrix(const std::vector<double>& tau) {
+  const int n = (int)tau.size();
+  std::vector<std::vector<double>> S(n - 1, std::vector<double>(n, 0.0));
+  for (int j = 0; j < n; ++j) {
+    std::vector<double> c(1, 1.0);  // power-series coefficients of l_j
+    for (int i = 0; i < n; ++i) {
+      if (i == j) continue;
+      const double den = tau[j] - tau[i];
+      std::vector<double> nc(c.size() + 1, 0.0);
+      for (size_t p = 0; p < c.size(); ++p) {
+        nc[p + 1] += c[p] / den;
+        nc[p] -= c[p] * tau[i] / den;
+      }
+      c.swap(nc);
+    }
+    auto anti = [&](double t) {
+      double s = 0.0, tp = t;
+      for (size_t p = 0; p < c.size(); ++p, tp *= t) s += c[p] * tp / double(p + 1);
+      return s;
+    };
+    for (int m = 0; m < n - 1; ++m) S[m][j] = anti(tau[m + 1]) - anti(tau[m]);
+  }
+  return S;
+}
+
+// ------------------------------------------------------------ kernel cache
+uint64_t fnv1a(const std::string& s, uint64_t h = 1469598103934665603ull) {
+  for (unsigned char c : s) {
+    h ^= c;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+std::string library_dir() {
+  Dl_info info;
+  if (dladdr((void*)&library_dir, &info) && info.dli_fname) {
+    std::string p(info.dli_fname);
+    auto k = p.rfind('/');
+    if (k != std::string::npos) return p.substr(0, k);
+  }
+  return ".";
+}
+
+std::string cache_dir() {
+  const char* e = std::getenv("SDC_KERNEL_CACHE");
+  if (e && *e) return e;
+  return library_dir() + "/_kcache";
+}
+
+const std::vector<const char*>& compile_options() {
+  static const std::vector<const char*> opts = {
+      "--offload-arch=gfx950", "-O3", "-std=c++17",
+      // no packed FP32 instructions
+      "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+  return opts;
+}
+
+std::mutex g_cache_mutex;
+std::map<uint64_t, std::vector<char>> g_code_cache;
+
+bool read_file(const std::string& path, std::vector<char>* out) {
+  std::ifstream f(path, std::ios::binary);
+  if (!f) return false;
+  out->assign(std::istreambuf_iterator<char>(f), std::istreambuf_iterator<char>());
+  return !out->empty();
+}
+
+void write_file_atomic(const std::string& dir, const std::string& name, const std::vector<char>& data) {
+  ::mkdir(dir.c_str(), 0755);
+  std::string tmp = dir + "/." + name + ".tmp" + std::to_string(::getpid());
+  {
+    std::ofstream f(tmp, std::ios::binary);
+    if (!f) return;
+    f.write(data.data(), (std::streamsize)data.size());
+    if (!f) return;
+  }
+  std::rename(tmp.c_str(), (dir + "/" + name).c_str());
+}
+
+// Code object for `src`: in-process cache, then the on-disk cache, then hipRTC.
+int get_code_object(const std::string& src, std::vector<char>* code, std::string* err) {
+  std::string key_text = src;
+  for (const char* o : compile_options()) key_text += std::string("\n//opt ") + o;
+  int ver_major = 0, ver_minor = 0;
+  hiprtcVersion(&ver_major, &ver_minor);
+  key_text += "\n//hiprtc " + std::to_string(ver_major) + "." + std::to_string(ver_minor);
+  const uint64_t key = fnv1a(key_text);
+  char name[64];
+  std::snprintf(name, sizeof name, "sdc_%016llx.co", (unsigned long long)key);
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mutex);
+    auto it = g_code_cache.find(key);
+    if (it != g_code_cache.end()) {
+      *code = it->second;
+      return SDC_OK;
+    }
+  }
+  const std::string dir = cache_dir();
+  if (read_file(dir + "/" + name, code)) {
+    std::lock_guard<std::mutex> lk(g_cache_mutex);
+    g_code_cache[key] = *code;
+    return SDC_OK;
+  }
+  hiprtcProgram prog;
+  if (hiprtcCreateProgram(&prog, src.c_str(), "sdc_kernels.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS) {
+    *err = "hiprtcCreateProgram failed";
+    return SDC_ERR_COMPILE;
+  }
+  const auto& opts = compile_options();
+  hiprtcResult rc = hiprtcCompileProgram(prog, (int)opts.size(), opts.data());
+  if (rc != HIPRTC_SUCCESS) {
+    size_t n = 0;
+    hiprtcGetProgramLogSize(prog, &n);
+    std::string log(n, '\0');
+    if (n) hiprtcGetProgramLog(prog, &log[0]);
+    hiprtcDestroyProgram(&prog);
+    *err = std::string("kernel compilation failed: ") + hiprtcGetErrorString(rc) + "\n" + log.substr(0, 4000);
+    return SDC_ERR_COMPILE;
+  }
+  size_t sz = 0;
+  hiprtcGetCodeSize(prog, &sz);
+  code->resize(sz);
+  hiprtcGetCode(prog, code->data());
+  hiprtcDestroyProgram(&prog);
+  write_file_atomic(dir, name, *code);
+  std::lock_guard<std::mutex> lk(g_cache_mutex);
+  g_code_cache[key] = *code;
+  return SDC_OK;
+}
+
+// ------------------------------------------------------------ validation
+struct Prepared {
+  sdc_config cfg;
+  sdcgen::Topology topo;
+  sdcgen::Pattern pat;
+  std::vector<double> lnA, b, E, Q, q;
+  int64_t Z = 0;
+  std::string source;
+};
+
+int prepare(const sdc_config* cfg, const sdc_network* net, Prepared* P, std::string* err) {
+  if (!cfg || !net) {
+    *err = "null configuration or network";
+    return SDC_ERR_ARG;
+  }
+  const sdc_config& c = *cfg;
+  if (c.dim < 1 || c.dim > 3) {
+    *err = "dim must be 1, 2 or 3";
+    return SDC_ERR_ARG;
+  }
+  int64_t Z = 1;
+  for (int d = 0; d < c.dim; ++d) {
+    const int64_t minn = c.advection ? 2 : 1;
+    if (c.n[d] < minn || c.n[d] > (int64_t(1) << 30)) {
+      *err = "zone counts must be in [2, 2^30] per direction (>= 1 without advection)";
+      return SDC_ERR_ARG;
+    }
+    if (!(c.dx[d] > 0.0) || !std::isfinite(c.dx[d])) {
+      *err = "dx must be positive and finite";
+      return SDC_ERR_ARG;
+    }
+    Z *= c.n[d];
+  }
+  if (Z > (int64_t(1) << 31) - (int64_t)kBlock) {
+    *err = "grid exceeds 2^31 zones";
+    return SDC_ERR_UNSUPPORTED;
+  }
+  if (!(c.gamma > 1.0) || !std::isfinite(c.gamma)) {
+    *err = "gamma must exceed 1";
+    return SDC_ERR_ARG;
+  }
+  if (c.n_nodes < 2 || c.n_nodes > SDC_MAX_NODES) {
+    *err = "n_nodes must be in 2..5";
+    return SDC_ERR_UNSUPPORTED;
+  }
+  if (c.n_iters < 1) {
+    *err = "n_iters must be >= 1";
+    return SDC_ERR_ARG;
+  }
+  if (c.precision != SDC_FP64 && c.precision != SDC_MIXED) {
+    *err = "precision must be SDC_FP64 or SDC_MIXED";
+    return SDC_ERR_ARG;
+  }
+  if ((c.advection != 0 && c.advection != 1) || (c.slope != 0 && c.slope != 1)) {
+    *err = "advection and slope must be 0 or 1";
+    return SDC_ERR_ARG;
+  }
+  if (!(c.newton_tol > 0.0) || c.newton_maxiter < 1 || !(c.pivot_threshold >= 0.0) || !std::isfinite(c.alpha)) {
+    *err = "newton_tol > 0, newton_maxiter >= 1, pivot_threshold >= 0 and finite alpha required";
+    return SDC_ERR_ARG;
+  }
+  const sdc_network& n = *net;
+  if (n.nspec < 1 || n.nspec > SDC_MAX_SPECIES || n.nreact < 0 || n.nreact > 4096) {
+    *err = "nspec must be in 1..31 and nreact in 0..4096";
+    return SDC_ERR_UNSUPPORTED;
+  }
+  if (n.nreact > 0 && (!n.reactants || !n.stoich || !n.lnA || !n.b || !n.E)) {
+    *err = "network arrays must not be NULL";
+    return SDC_ERR_ARG;
+  }
+  if (!n.q) {
+    *err = "network q must not be NULL";
+    return SDC_ERR_ARG;
+  }
+  P->cfg = c;
+  P->Z = Z;
+  auto& t = P->topo;
+  t.ns = n.nspec;
+  t.nr = n.nreact;
+  t.reactants.resize(n.nreact);
+  t.stoich.assign(n.stoich, n.stoich + (size_t)n.nreact * n.nspec);
+  for (int r = 0; r < n.nreact; ++r) {
+    const int a = n.reactants[2 * r], cc = n.reactants[2 * r + 1];
+    if (a < 0 || a >= n.nspec || cc < -1 || cc >= n.nspec) {
+      *err = "reactant index out of range in reaction " + std::to_string(r);
+      return SDC_ERR_ARG;
+    }
+    t.reactants[r] = {a, cc};
+    for (int i = 0; i < n.nspec; ++i)
+      if (!std::isfinite(t.stoich[(size_t)r * n.nspec + i])) {
+        *err = "non-finite stoichiometric coefficient";
+        return SDC_ERR_ARG;
+      }
+  }
+  P->q.assign(n.q, n.q + n.nspec);
+  P->lnA.assign(n.lnA ? n.lnA : nullptr, n.lnA ? n.lnA + n.nreact : nullptr);
+  P->b.assign(n.b ? n.b : nullptr, n.b ? n.b + n.nreact : nullptr);
+  P->E.assign(n.E ? n.E : nullptr, n.E ? n.E + n.nreact : nullptr);
+  P->Q.assign(n.nreact, 0.0);
+  for (int r = 0; r < n.nreact; ++r) {
+    double s = 0.0;
+    for (int i = 0; i < n.nspec; ++i) s -= t.stoich[(size_t)r * n.nspec + i] * P->q[i];
+    P->Q[r] = s;
+  }
+  P->pat = sdcgen::build_pattern(t);
+  std::ostringstream src;
+  src << "// SDC kernels: dim " << c.dim << ", " << c.n_nodes << " nodes, "
+      << (c.precision == SDC_MIXED ? "mixed" : "fp64") << "\n";
+  src << "#define SDC_DIM " << c.dim << "\n#define SDC_NNODES " << c.n_nodes << "\n";
+  if (c.precision == SDC_MIXED) src << "#define SDC_MIXED 1\n";
+  src << kSdcArgsSrc << "\n" << sdcgen::generate(t, P->pat) << "\n";
+  std::string dev = kSdcDeviceSrc;
+  const std::string inc = "#include \"sdc_args.h\"";
+  auto k = dev.find(inc);
+  if (k != std::string::npos) dev.replace(k, inc.size(), "// (argument blocks defined above)");
+  src << dev;
+  P->source = src.str();
+  return SDC_OK;
+}
+
+std::vector<double> params_image(const Prepared& P, int nr_alloc) {
+  // NetParams layout: lnA[NRA], b[NRA], E[NRA], Q[NRA], q[NS]
+  const int nr = P.topo.nr;
+  std::vector<double> img((size_t)4 * nr_alloc + P.topo.ns, 0.0);
+  for (int r = 0; r < nr; ++r) {
+    img[r] = P.lnA[r];
+    img[nr_alloc + r] = P.b[r];
+    img[2 * nr_alloc + r] = P.E[r];
+    img[3 * nr_alloc + r] = P.Q[r];
+  }
+  for (int i = 0; i < P.topo.ns; ++i) img[4 * nr_alloc + i] = P.q[i];
+  return img;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ handle
+struct sdc_handle_s {
+  Prepared P;
+  int ns = 0, nc = 0, nx = 0, M = 0, nra = 1;
+  std::vector<double> tau;
+  std::vector<std::vector<double>> S;
+  hipModule_t mod = nullptr;
+  hipFunction_t f_advect = nullptr, f_source = nullptr, f_solve = nullptr, f_first = nullptr,
+                f_node0 = nullptr, f_later = nullptr, f_fill = nullptr;
+  void* d_params = nullptr;
+  unsigned long long* d_stats = nullptr;
+  hipStream_t last_stream = nullptr;
+  std::string err;
+  // per-kernel timing
+  bool profile = false;
+  struct Timed {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Timed> timed;
+  std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+int fail(sdc_handle h, int code, const std::string& msg) {
+  if (h)
+    h->err = msg;
+  else
+    g_init_error = msg;
+  return code;
+}
+
+#define HIP_CHECK(h, expr)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(h, SDC_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int kind_of(const sdc_handle h, hipFunction_t f) {
+  if (f == h->f_advect) return SDC_K_ADVECT;
+  if (f == h->f_source) return SDC_K_SOURCE;
+  if (f == h->f_solve) return SDC_K_SOLVE;
+  if (f == h->f_first) return SDC_K_TRANSITION_FIRST;
+  if (f == h->f_node0) return SDC_K_TRANSITION_NODE0;
+  if (f == h->f_later) return SDC_K_TRANSITION_LATER;
+  return SDC_K_FILL;
+}
+
+hipEvent_t take_event(sdc_handle h) {
+  if (!h->event_pool.empty()) {
+    hipEvent_t e = h->event_pool.back();
+    h->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int launch(sdc_handle h, hipFunction_t f, int64_t nthreads, void* args, hipStream_t s) {
+  if (nthreads <= 0) return SDC_OK;
+  const int64_t nb = (nthreads + kBlock - 1) / kBlock;
+  void* params[] = {args};
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (h->profile) {
+    ea = take_event(h);
+    eb = take_event(h);
+    if (!ea || !eb) return fail(h, SDC_ERR_HIP, "hipEventCreate failed");
+    HIP_CHECK(h, hipEventRecord(ea, s));
+  }
+  HIP_CHECK(h, hipModuleLaunchKernel(f, (unsigned)nb, 1, 1, kBlock, 1, 1, 0, s, params, nullptr));
+  if (h->profile) {
+    HIP_CHECK(h, hipEventRecord(eb, s));
+    h->timed.push_back({kind_of(h, f), ea, eb});
+  }
+  return SDC_OK;
+}
+
+int fill(sdc_handle h, double* p, int64_t n, double v, hipStream_t s) {
+  FillArgs a{p, n, v};
+  return launch(h, h->f_fill, n, &a, s);
+}
+
+NewtonCtl newton_ctl(const sdc_handle h) {
+  NewtonCtl c;
+  c.tol = h->P.cfg.newton_tol;
+  c.tau = h->P.cfg.pivot_threshold;
+  c.maxiter = h->P.cfg.newton_maxiter;
+  return c;
+}
+
+int advect(sdc_handle h, const double* U, double* A, hipStream_t s) {
+  const sdc_config& c = h->P.cfg;
+  if (!c.advection) return fill(h, A, (int64_t)h->nc * h->P.Z, 0.0, s);
+  AdvArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.U = U;
+  a.A = A;
+  a.Z = h->P.Z;
+  for (int d = 0; d < 3; ++d) {
+    a.n[d] = d < c.dim ? (int)c.n[d] : 1;
+    a.idx[d] = d < c.dim ? 1.0 / c.dx[d] : 0.0;
+  }
+  a.gamma = c.gamma;
+  a.alpha = c.alpha;
+  a.slope = c.slope;
+  return launch(h, h->f_advect, h->P.Z, &a, s);
+}
+
+int source(sdc_handle h, const double* U, double* R, hipStream_t s) {
+  SourceArgs a{h->P.Z, U, R, h->d_params, h->P.cfg.gamma - 1.0};
+  return launch(h, h->f_source, h->P.Z, &a, s);
+}
+
+bool nodes_ok(const sdc_handle h, const sdc_nodes* n, bool need_c) {
+  for (int j = 0; j <= h->M; ++j)
+    if (!n->U[j] || !n->A[j] || !n->R[j]) return false;
+  if (need_c)
+    for (int j = 0; j < h->M - 1; ++j)
+      if (!n->C[j]) return false;
+  return true;
+}
+
+// One iteration k -> k+1 over the M transitions, then A at node M.
+int sweep(sdc_handle h, double dt, int k, const sdc_nodes& n, hipStream_t s) {
+  const int M = h->M;
+  for (int m = 0; m < M; ++m) {
+    TransArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.Z = h->P.Z;
+    a.m = m;
+    a.M = M;
+    a.first = k == 0;
+    a.dt = dt;
+    a.dtm = (h->tau[m + 1] - h->tau[m]) * dt;
+    for (int i = 0; i < M; ++i) {
+      for (int j = 0; j <= M; ++j) a.S[i][j] = h->S[i][j];
+      a.dtj[i] = (h->tau[i + 1] - h->tau[i]) * dt;
+    }
+    a.Um = n.U[m];
+    a.Am = n.A[m];
+    for (int j = 0; j <= M; ++j) {
+      a.Aold[j] = n.A[j];
+      a.Rold[j] = n.R[j];
+    }
+    if (m >= 1 && k >= 1) a.Cin = n.C[m - 1];
+    for (int j = 1; j < M; ++j) a.Cout[j - 1] = n.C[j - 1];
+    a.guess = k == 0 ? n.U[0] : n.U[m + 1];
+    a.Uout = n.U[m + 1];
+    a.Rout = n.R[m + 1];
+    a.P = h->d_params;
+    a.gm1 = h->P.cfg.gamma - 1.0;
+    a.ctl = newton_ctl(h);
+    a.stats = h->d_stats;
+    hipFunction_t f = k == 0 ? h->f_first : (m == 0 ? h->f_node0 : h->f_later);
+    int rc = launch(h, f, h->P.Z, &a, s);
+    if (rc) return rc;
+    if (h->P.cfg.advection) {
+      rc = advect(h, n.U[m + 1], n.A[m + 1], s);
+      if (rc) return rc;
+    }
+  }
+  return SDC_OK;
+}
+
+int check_handle(sdc_handle h) {
+  if (!h) return fail(nullptr, SDC_ERR_ARG, "null handle");
+  return SDC_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+int sdc_config_default(sdc_config* cfg) {
+  if (!cfg) return SDC_ERR_ARG;
+  std::memset(cfg, 0, sizeof *cfg);
+  cfg->dim = 1;
+  cfg->n[0] = cfg->n[1] = cfg->n[2] = 1;
+  cfg->dx[0] = cfg->dx[1] = cfg->dx[2] = 1.0;
+  cfg->gamma = 1.4;
+  cfg->n_nodes = 3;
+  cfg->n_iters = 4;
+  cfg->precision = SDC_FP64;
+  cfg->advection = 1;
+  cfg->slope = 1;
+  cfg->alpha = -1.0;
+  cfg->newton_tol = 1e-13;
+  cfg->newton_maxiter = 50;
+  cfg->pivot_threshold = 0.1;
+  return SDC_OK;
+}
+
+int64_t sdc_generated_source(const sdc_config* cfg, const sdc_network* net, char* buf, int64_t len) {
+  Prepared P;
+  std::string err;
+  int rc = prepare(cfg, net, &P, &err);
+  if (rc) {
+    g_init_error = err;
+    return -rc;
+  }
+  const int64_t need = (int64_t)P.source.size() + 1;
+  if (buf && len > 0) {
+    const int64_t n = need < len ? need : len;
+    std::memcpy(buf, P.source.c_str(), (size_t)n - 1);
+    buf[n - 1] = '\0';
+  }
+  return need;
+}
+
+int sdc_compile_only(const sdc_config* cfg, const sdc_network* net) {
+  Prepared P;
+  std::string err;
+  int rc = prepare(cfg, net, &P, &err);
+  if (rc) return fail(nullptr, rc, err);
+  std::vector<char> code;
+  rc = get_code_object(P.source, &code, &err);
+  if (rc) return fail(nullptr, rc, err);
+  return SDC_OK;
+}
+
+int sdc_init(const sdc_config* cfg, const sdc_network* net, sdc_handle* out) {
+  if (!out) return fail(nullptr, SDC_ERR_ARG, "null output handle");
+  *out = nullptr;
+  auto* h = new (std::nothrow) sdc_handle_s;
+  if (!h) return fail(nullptr, SDC_ERR_NOMEM, "host allocation failed");
+  std::string err;
+  int rc = prepare(cfg, net, &h->P, &err);
+  if (rc) {
+    delete h;
+    return fail(nullptr, rc, err);
+  }
+  h->ns = h->P.topo.ns;
+  h->nc = 2 + h->P.cfg.dim + h->ns;
+  h->nx = h->ns + 1;
+  h->M = h->P.cfg.n_nodes - 1;
+  h->nra = h->P.topo.nr > 0 ? h->P.topo.nr : 1;
+  h->tau = lobatto_nodes(h->P.cfg.n_nodes);
+  h->S = integration_matrix(h->tau);
+  std::vector<char> code;
+  rc = get_code_object(h->P.source, &code, &err);
+  if (rc) {
+    delete h;
+    return fail(nullptr, rc, err);
+  }
+  auto bail = [&](int code_, const std::string& msg) {
+    sdc_destroy(h);
+    return fail(nullptr, code_, msg);
+  };
+  hipError_t e = hipModuleLoadData(&h->mod, code.data());
+  if (e != hipSuccess) return bail(SDC_ERR_HIP, std::string("hipModuleLoadData: ") + hipGetErrorString(e));
+  struct {
+    hipFunction_t* f;
+    const char* name;
+  } fns[] = {{&h->f_advect, "sdc_advect"},         {&h->f_source, "sdc_source"},
+             {&h->f_solve, "sdc_reaction_solve"},  {&h->f_first, "sdc_transition_first"},
+             {&h->f_node0, "sdc_transition_node0"}, {&h->f_later, "sdc_transition_later"},
+             {&h->f_fill, "sdc_fill"}};
+  for (auto& fn : fns) {
+    e = hipModuleGetFunction(fn.f, h->mod, fn.name);
+    if (e != hipSuccess) return bail(SDC_ERR_HIP, std::string("missing kernel ") + fn.name);
+  }
+  const std::vector<double> img = params_image(h->P, h->nra);
+  e = hipMalloc(&h->d_params, img.size() * sizeof(double));
+  if (e != hipSuccess) return bail(SDC_ERR_NOMEM, "hipMalloc(params) failed");
+  e = hipMemcpy(h->d_params, img.data(), img.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return bail(SDC_ERR_HIP, std::string("hipMemcpy(params): ") + hipGetErrorString(e));
+  e = hipMalloc((void**)&h->d_stats, SDC_NSTATS * sizeof(unsigned long long));
+  if (e != hipSuccess) return bail(SDC_ERR_NOMEM, "hipMalloc(stats) failed");
+  e = hipMemset(h->d_stats, 0, SDC_NSTATS * sizeof(unsigned long long));
+  if (e != hipSuccess) return bail(SDC_ERR_HIP, std::string("hipMemset(stats): ") + hipGetErrorString(e));
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) return bail(SDC_ERR_HIP, std::string("hipDeviceSynchronize: ") + hipGetErrorString(e));
+  *out = h;
+  return SDC_OK;
+}
+
+int sdc_destroy(sdc_handle h) {
+  if (!h) return SDC_OK;
+  if (h->last_stream) (void)hipStreamSynchronize(h->last_stream);
+  (void)hipDeviceSynchronize();
+  for (auto& t : h->timed) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (auto e : h->event_pool) (void)hipEventDestroy(e);
+  if (h->d_params) (void)hipFree(h->d_params);
+  if (h->d_stats) (void)hipFree(h->d_stats);
+  if (h->mod) (void)hipModuleUnload(h->mod);
+  delete h;
+  return SDC_OK;
+}
+
+const char* sdc_last_error(sdc_handle h) { return h ? h->err.c_str() : g_init_error.c_str(); }
+
+int sdc_sizes(sdc_handle h, int64_t* zones, int32_t* ncomp, int32_t* nreact_vars) {
+  if (int rc = check_handle(h)) return rc;
+  if (zones) *zones = h->P.Z;
+  if (ncomp) *ncomp = h->nc;
+  if (nreact_vars) *nreact_vars = h->nx;
+  return SDC_OK;
+}
+
+int sdc_advective_term(sdc_handle h, const double* U, double* A, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!U || !A) return fail(h, SDC_ERR_ARG, "null array");
+  if (U == A) return fail(h, SDC_ERR_ARG, "U and A must not alias");
+  h->last_stream = (hipStream_t)stream;
+  return advect(h, U, A, (hipStream_t)stream);
+}
+
+int sdc_source(sdc_handle h, const double* U, double* R, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!U || !R) return fail(h, SDC_ERR_ARG, "null array");
+  h->last_stream = (hipStream_t)stream;
+  return source(h, U, R, (hipStream_t)stream);
+}
+
+int sdc_reaction_solve(sdc_handle h, double dt_m, const double* rho, const double* b, double* x, double* R,
+                       int32_t* iters, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!rho || !b || !x || !R || !iters) return fail(h, SDC_ERR_ARG, "null array");
+  if (!std::isfinite(dt_m) || dt_m < 0.0) return fail(h, SDC_ERR_ARG, "dt_m must be finite and >= 0");
+  if ((const double*)x == b) return fail(h, SDC_ERR_ARG, "x and b must not alias");
+  h->last_stream = (hipStream_t)stream;
+  SolveArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.Z = h->P.Z;
+  a.dtm = dt_m;
+  a.rho = rho;
+  a.b = b;
+  a.x = x;
+  a.R = R;
+  a.iters = iters;
+  a.P = h->d_params;
+  a.gm1 = h->P.cfg.gamma - 1.0;
+  a.ctl = newton_ctl(h);
+  a.stats = h->d_stats;
+  return launch(h, h->f_solve, h->P.Z, &a, (hipStream_t)stream);
+}
+
+int sdc_sweep(sdc_handle h, double dt, int32_t k, const sdc_nodes* nodes, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!nodes || k < 0) return fail(h, SDC_ERR_ARG, "null nodes or negative k");
+  if (!std::isfinite(dt) || dt <= 0.0) return fail(h, SDC_ERR_ARG, "dt must be positive");
+  if (!nodes_ok(h, nodes, k >= 1 && h->M >= 2)) return fail(h, SDC_ERR_ARG, "missing node arrays");
+  h->last_stream = (hipStream_t)stream;
+  return sweep(h, dt, k, *nodes, (hipStream_t)stream);
+}
+
+int sdc_step(sdc_handle h, double dt, int32_t nsteps, double* U, const sdc_nodes* work, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!U || !work || nsteps < 0) return fail(h, SDC_ERR_ARG, "null U/work or negative nsteps");
+  if (!std::isfinite(dt) || dt <= 0.0) return fail(h, SDC_ERR_ARG, "dt must be positive");
+  if (!nodes_ok(h, work, h->P.cfg.n_iters >= 2 && h->M >= 2)) return fail(h, SDC_ERR_ARG, "missing node arrays");
+  for (int j = 0; j <= h->M; ++j)
+    if (work->U[j] == U) return fail(h, SDC_ERR_ARG, "work arrays must not alias U");
+  if (nsteps == 0) return SDC_OK;
+  hipStream_t s = (hipStream_t)stream;
+  h->last_stream = s;
+  sdc_nodes n = *work;
+  const size_t bytesU = (size_t)h->nc * h->P.Z * sizeof(double);
+  HIP_CHECK(h, hipMemcpyAsync(n.U[0], U, bytesU, hipMemcpyDeviceToDevice, s));
+  int rc = advect(h, n.U[0], n.A[0], s);
+  if (rc) return rc;
+  rc = source(h, n.U[0], n.R[0], s);
+  if (rc) return rc;
+  if (!h->P.cfg.advection)
+    for (int j = 1; j <= h->M; ++j)
+      if ((rc = fill(h, n.A[j], (int64_t)h->nc * h->P.Z, 0.0, s))) return rc;
+  for (int step = 0; step < nsteps; ++step) {
+    for (int k = 0; k < h->P.cfg.n_iters; ++k)
+      if ((rc = sweep(h, dt, k, n, s))) return rc;
+    // the last node becomes node 0 of the next step
+    std::swap(n.U[0], n.U[h->M]);
+    std::swap(n.A[0], n.A[h->M]);
+    std::swap(n.R[0], n.R[h->M]);
+  }
+  HIP_CHECK(h, hipMemcpyAsync(U, n.U[0], bytesU, hipMemcpyDeviceToDevice, s));
+  return SDC_OK;
+}
+
+int sdc_stats(sdc_handle h, int64_t* out) {
+  if (int rc = check_handle(h)) return rc;
+  if (!out) return fail(h, SDC_ERR_ARG, "null output");
+  if (h->last_stream) HIP_CHECK(h, hipStreamSynchronize(h->last_stream));
+  HIP_CHECK(h, hipDeviceSynchronize());
+  unsigned long long tmp[SDC_NSTATS];
+  HIP_CHECK(h, hipMemcpy(tmp, h->d_stats, sizeof tmp, hipMemcpyDeviceToHost));
+  for (int i = 0; i < SDC_NSTATS; ++i) out[i] = (int64_t)tmp[i];
+  return SDC_OK;
+}
+
+int sdc_stats_reset(sdc_handle h, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  h->last_stream = (hipStream_t)stream;
+  HIP_CHECK(h, hipMemsetAsync(h->d_stats, 0, SDC_NSTATS * sizeof(unsigned long long), (hipStream_t)stream));
+  return SDC_OK;
+}
+
+int sdc_set_params(sdc_handle h, const double* lnA, const double* E) {
+  if (int rc = check_handle(h)) return rc;
+  const int nr = h->P.topo.nr;
+  if (nr > 0 && (!lnA || !E)) return fail(h, SDC_ERR_ARG, "null parameter array");
+  for (int r = 0; r < nr; ++r)
+    if (!std::isfinite(lnA[r]) || !std::isfinite(E[r])) return fail(h, SDC_ERR_ARG, "non-finite parameter");
+  h->P.lnA.assign(lnA, lnA + nr);
+  h->P.E.assign(E, E + nr);
+  const std::vector<double> img = params_image(h->P, h->nra);
+  if (h->last_stream) HIP_CHECK(h, hipStreamSynchronize(h->last_stream));
+  HIP_CHECK(h, hipMemcpy(h->d_params, img.data(), img.size() * sizeof(double), hipMemcpyHostToDevice));
+  return SDC_OK;
+}
+
+int sdc_profile_enable(sdc_handle h, int32_t enable) {
+  if (int rc = check_handle(h)) return rc;
+  h->profile = enable != 0;
+  return SDC_OK;
+}
+
+int sdc_profile_read(sdc_handle h, double* ms, int64_t* launches) {
+  if (int rc = check_handle(h)) return rc;
+  if (!ms || !launches) return fail(h, SDC_ERR_ARG, "null output");
+  for (int k = 0; k < SDC_NKINDS; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  for (auto& t : h->timed) {
+    HIP_CHECK(h, hipEventSynchronize(t.b));
+    float v = 0.0f;
+    HIP_CHECK(h, hipEventElapsedTime(&v, t.a, t.b));
+    ms[t.kind] += v;
+    launches[t.kind] += 1;
+    h->event_pool.push_back(t.a);
+    h->event_pool.push_back(t.b);
+  }
+  h->timed.clear();
+  return SDC_OK;
+}
+
+int sdc_cost_model(sdc_handle h, int64_t* out) {
+  if (int rc = check_handle(h)) return rc;
+  if (!out) return fail(h, SDC_ERR_ARG, "null output");
+  const sdcgen::FlopCount f = sdcgen::count_flops(h->P.topo, h->P.pat);
+  out[0] = f.source;
+  out[1] = f.residual_matrix;
+  out[2] = f.lu;
+  out[3] = f.solve;
+  out[4] = f.exps;
+  out[5] = h->P.pat.nnz_jac;
+  out[6] = h->P.pat.nnz;
+  return SDC_OK;
+}
+
+}  // extern "C"

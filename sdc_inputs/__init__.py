@@ -240,11 +240,16 @@ def box_state(extents, nspec, seed=SEEDS["boxes_state"] + 1, sigma=0.3, vel=0.05
 
 
 # ---------------------------------------------------------------- workloads
+FULL_SHAPES = {"chain1d": (64,), "net2d": (512, 512), "adjoint2d": (256, 256), "net3d": (256, 256, 256)}
+
+
 def workload(name: str, shape=None, steps=None) -> dict:
     """Everything one run needs: grid, network, U0 [n_c, *grid], dt and knobs.
 
     `shape` overrides the grid (x first) for reduced-size parity cases that
-    keep the workload's recipe.
+    keep the workload's recipe.  The time step is always the CFL step of the
+    full-size grid (the drawn state's signal speeds with the full grid's dx),
+    so reduced cases see the same reaction stiffness per step as the real run.
     """
     if name == "chain1d":
         shape = shape or (64,)
@@ -269,12 +274,13 @@ def workload(name: str, shape=None, steps=None) -> dict:
         raise ValueError(f"unknown workload {name!r}")
     dim = len(shape)
     dx = [1.0 / n for n in shape]
+    dx_full = [1.0 / n for n in FULL_SHAPES[name]]
     U0 = conserved_from_primitive(rho, u, p, X)
     alpha = -1.0
     if d["slope"] == 0:
         alpha = 1.2 * max_signal_speed(rho, u, p)
     out = dict(name=name, dim=dim, shape=tuple(shape), dx=dx, gamma=GAMMA,
-               network=net, U0=U0, dt=cfl_dt(rho, u, p, dx, cfl=d["cfl"]),
+               network=net, U0=U0, dt=cfl_dt(rho, u, p, dx_full, cfl=d["cfl"]),
                alpha=alpha, newton_tol=1e-13, newton_maxiter=50, **d)
     if steps is not None:
         out["steps"] = steps
