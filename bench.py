@@ -130,6 +130,8 @@ def main():
     ap.add_argument("--precision", default="both", choices=("fp64", "mixed", "both"))
     ap.add_argument("--cpu-edge", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one device copy of this many MiB (calibrates HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {a.gpus}); multi-GPU sharding is a design "
@@ -174,6 +176,16 @@ def main():
                             speedup_vs_fp64=runs["mixed"]["zone_updates"] / runs["fp64"]["zone_updates"],
                             mean_newton_iterations=runs["mixed"]["mean_newton"],
                             kernels_ms=runs["mixed"]["profile"])
+    if a.copy_probe_mib:
+        import torch
+        n = a.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 8 * n
+        del src, dst
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_edge)

@@ -192,6 +192,210 @@ extern "C" __global__ __launch_bounds__(256) void sdc_advect(AdvArgs a) {
   }
 }
 
+#if SDC_DIM == 3
+// ---- 3D advective term, z-marching.  A block of 64 x 4 threads owns a 64 x 4
+// column tile and walks SDC_ZCHUNK planes in z.  Plane k of every component is
+// staged in LDS with a two-zone x/y halo for the x and y stencils; each thread
+// carries its column's z window (U_k, U_{k+1}, the z slope at k and the flux
+// through face k-1/2) in registers, so every value crosses HBM about once.
+#define ZT_X 64
+#define ZT_Y 4
+#define SDC_ZCHUNK 32
+
+// Rusanov flux of the hydro components through one face from the two
+// reconstructed states, plus the face data the species fluxes need.
+__device__ __forceinline__ void hydro_face(const double* WL, const double* WR, int d, double gamma, double alpha,
+                                           double* F, FaceHydro& fh) {
+  double FL[SDC_NH], FR[SDC_NH], pL, pR, cL, cR;
+  hydro_flux(WL, d, gamma, FL, fh.uL, pL, cL);
+  hydro_flux(WR, d, gamma, FR, fh.uR, pR, cR);
+  fh.a = alpha > 0.0 ? alpha : fmax(fabs(fh.uL) + cL, fabs(fh.uR) + cR);
+#pragma unroll
+  for (int q = 0; q < SDC_NH; ++q) F[q] = 0.5 * (FL[q] + FR[q]) - 0.5 * fh.a * (WR[q] - WL[q]);
+}
+
+__device__ __forceinline__ double species_face(double L, double R, const FaceHydro& f) {
+  return 0.5 * (L * f.uL + R * f.uR) - 0.5 * f.a * (R - L);
+}
+
+// Species are processed in groups of up to SDC_SPG per block (the group index
+// is part of the grid): every group recomputes the hydro faces, which costs
+// re-reading the few hydro components but keeps the carried z windows small.
+#define SDC_SPG (SDC_NS < 5 ? SDC_NS : 5)
+#define SDC_NGRP ((SDC_NS + SDC_SPG - 1) / SDC_SPG)
+#define SDC_TC (SDC_NH + SDC_SPG)  // components staged per block
+
+extern "C" __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void sdc_advect3d(AdvArgs a) {
+  __shared__ double tile[SDC_TC][ZT_Y + 4][ZT_X + 4];
+  const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+  const int tx = threadIdx.x % ZT_X, ty = threadIdx.x / ZT_X;
+  const int nbx = (n0 + ZT_X - 1) / ZT_X, nby = (n1 + ZT_Y - 1) / ZT_Y;
+  const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+  const int grp = (int)(lb % SDC_NGRP);
+  const unsigned tb = lb / SDC_NGRP;
+  const int bx = (int)(tb % nbx), by = (int)((tb / nbx) % nby), bz = (int)(tb / (nbx * nby));
+  const int i = bx * ZT_X + tx, j = by * ZT_Y + ty;
+  const bool active = i < n0 && j < n1;
+  const int z0 = bz * SDC_ZCHUNK;
+  const int z1 = min(z0 + SDC_ZCHUNK, n2);
+  // 32-bit element offsets inside one component array (the host checks Z < 2^28):
+  // loads then take a uniform base plus a 32-bit per-lane offset
+  const int P = n0 * n1;
+  const i64 Z = a.Z;
+  const double* __restrict__ U = a.U;
+  // A tile position past the grid edge holds the periodic image of the grid
+  // (coordinates mod n), so every halo slot is the periodic neighbour of the
+  // zones next to it, also in ragged tiles; such positions compute but never store.
+  auto pmod = [](int v, int n) { return ((v % n) + n) % n; };
+  auto wrap = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
+  const int ic = pmod(i, n0), jc = pmod(j, n1);
+  const int col = jc * n0 + ic;
+  const int hy_row = ty < 2 ? by * ZT_Y - 2 + ty : by * ZT_Y + ZT_Y + (ty - 2);
+  const int hy = pmod(hy_row, n1) * n0 + ic;
+  const int hy_slot = ty < 2 ? ty : ZT_Y + 2 + (ty - 2);
+  const bool hx_on = tx < 2 || tx >= ZT_X - 2;
+  const int hx_colg = tx < 2 ? bx * ZT_X - 2 + tx : bx * ZT_X + ZT_X + (tx - (ZT_X - 2));
+  const int hx = jc * n0 + pmod(hx_colg, n0);
+  const int hx_slot = tx < 2 ? tx : ZT_X + 2 + (tx - (ZT_X - 2));
+  const double idx = a.idx[0], idy = a.idx[1], idz = a.idx[2];
+  // component of slot t: hydro first, then this block's species
+  auto comp = [&](int t) { return t < SDC_NH ? t : SDC_NH + grp * SDC_SPG + (t - SDC_NH); };
+  auto valid = [&](int t) { return t < SDC_NH || grp * SDC_SPG + (t - SDC_NH) < SDC_NS; };
+
+  double Uk[SDC_TC], Uk1[SDC_TC], dUk[SDC_TC], Fm[SDC_TC];
+  {
+    const int pm2 = wrap(z0 - 2, n2) * P, pm1 = wrap(z0 - 1, n2) * P;
+    const int p0 = z0 * P, p1 = wrap(z0 + 1, n2) * P;
+    double Wm[SDC_TC], WL[SDC_NH], WR[SDC_NH];
+#pragma unroll
+    for (int t = 0; t < SDC_TC; ++t) {
+      const double* Uc = U + (i64)(valid(t) ? comp(t) : 0) * Z;
+      const double um2 = Uc[pm2 + col], um1 = Uc[pm1 + col];
+      Uk[t] = Uc[p0 + col];
+      Uk1[t] = Uc[p1 + col];
+      const double dm1 = slope_of(um2, um1, Uk[t], a.slope);
+      dUk[t] = slope_of(um1, Uk[t], Uk1[t], a.slope);
+      Wm[t] = um1 + 0.5 * dm1;
+    }
+#pragma unroll
+    for (int q = 0; q < SDC_NH; ++q) {
+      WL[q] = Wm[q];
+      WR[q] = Uk[q] - 0.5 * dUk[q];
+    }
+    FaceHydro f;
+    hydro_face(WL, WR, 2, a.gamma, a.alpha, Fm, f);
+#pragma unroll
+    for (int t = SDC_NH; t < SDC_TC; ++t) Fm[t] = species_face(Wm[t], Uk[t] - 0.5 * dUk[t], f);
+  }
+
+  for (int k = z0; k < z1; ++k) {
+    const int pk = k * P, p2 = wrap(k + 2, n2) * P;
+#pragma unroll
+    for (int t = 0; t < SDC_TC; ++t) {
+      const double* Uc = U + (i64)(valid(t) ? comp(t) : 0) * Z;
+      tile[t][ty + 2][tx + 2] = Uk[t];
+      tile[t][hy_slot][tx + 2] = Uc[pk + hy];
+      if (hx_on) tile[t][ty + 2][hx_slot] = Uc[pk + hx];
+    }
+    __syncthreads();
+    double acc[SDC_NH];
+    FaceHydro fx[2], fy[2], fz;
+    {
+      double WL[2][SDC_NH], WR[2][SDC_NH];
+#pragma unroll
+      for (int q = 0; q < SDC_NH; ++q) {
+        const double* r = &tile[q][ty + 2][tx];
+        const double sm = slope_of(r[0], r[1], r[2], a.slope);
+        const double s0 = slope_of(r[1], r[2], r[3], a.slope);
+        const double sp = slope_of(r[2], r[3], r[4], a.slope);
+        WL[0][q] = r[1] + 0.5 * sm;
+        WR[0][q] = r[2] - 0.5 * s0;
+        WL[1][q] = r[2] + 0.5 * s0;
+        WR[1][q] = r[3] - 0.5 * sp;
+      }
+      double F0[SDC_NH], F1[SDC_NH];
+      hydro_face(WL[0], WR[0], 0, a.gamma, a.alpha, F0, fx[0]);
+      hydro_face(WL[1], WR[1], 0, a.gamma, a.alpha, F1, fx[1]);
+#pragma unroll
+      for (int q = 0; q < SDC_NH; ++q) acc[q] = -(F1[q] - F0[q]) * idx;
+#pragma unroll
+      for (int q = 0; q < SDC_NH; ++q) {
+        const double v0 = tile[q][ty][tx + 2], v1 = tile[q][ty + 1][tx + 2], v2 = tile[q][ty + 2][tx + 2];
+        const double v3 = tile[q][ty + 3][tx + 2], v4 = tile[q][ty + 4][tx + 2];
+        const double sm = slope_of(v0, v1, v2, a.slope);
+        const double s0 = slope_of(v1, v2, v3, a.slope);
+        const double sp = slope_of(v2, v3, v4, a.slope);
+        WL[0][q] = v1 + 0.5 * sm;
+        WR[0][q] = v2 - 0.5 * s0;
+        WL[1][q] = v2 + 0.5 * s0;
+        WR[1][q] = v3 - 0.5 * sp;
+      }
+      hydro_face(WL[0], WR[0], 1, a.gamma, a.alpha, F0, fy[0]);
+      hydro_face(WL[1], WR[1], 1, a.gamma, a.alpha, F1, fy[1]);
+#pragma unroll
+      for (int q = 0; q < SDC_NH; ++q) acc[q] -= (F1[q] - F0[q]) * idy;
+      double dUk1[SDC_NH];
+#pragma unroll
+      for (int q = 0; q < SDC_NH; ++q) {
+        const double u2 = (U + (i64)q * Z)[p2 + col];
+        dUk1[q] = slope_of(Uk[q], Uk1[q], u2, a.slope);
+        WL[0][q] = Uk[q] + 0.5 * dUk[q];
+        WR[0][q] = Uk1[q] - 0.5 * dUk1[q];
+        Uk[q] = Uk1[q];
+        Uk1[q] = u2;
+      }
+      hydro_face(WL[0], WR[0], 2, a.gamma, a.alpha, F1, fz);
+#pragma unroll
+      for (int q = 0; q < SDC_NH; ++q) {
+        acc[q] -= (F1[q] - Fm[q]) * idz;
+        Fm[q] = F1[q];
+        dUk[q] = dUk1[q];
+      }
+      if (active && grp == 0)
+#pragma unroll
+        for (int q = 0; q < SDC_NH; ++q) (a.A + (i64)q * Z)[pk + col] = acc[q];
+    }
+#pragma unroll
+    for (int t = SDC_NH; t < SDC_TC; ++t) {
+      const bool ok = valid(t);
+      const int c = ok ? comp(t) : 0;
+      double As;
+      {
+        const double* r = &tile[t][ty + 2][tx];
+        const double sm = slope_of(r[0], r[1], r[2], a.slope);
+        const double s0 = slope_of(r[1], r[2], r[3], a.slope);
+        const double sp = slope_of(r[2], r[3], r[4], a.slope);
+        const double F0 = species_face(r[1] + 0.5 * sm, r[2] - 0.5 * s0, fx[0]);
+        const double F1 = species_face(r[2] + 0.5 * s0, r[3] - 0.5 * sp, fx[1]);
+        As = -(F1 - F0) * idx;
+      }
+      {
+        const double v0 = tile[t][ty][tx + 2], v1 = tile[t][ty + 1][tx + 2], v2 = tile[t][ty + 2][tx + 2];
+        const double v3 = tile[t][ty + 3][tx + 2], v4 = tile[t][ty + 4][tx + 2];
+        const double sm = slope_of(v0, v1, v2, a.slope);
+        const double s0 = slope_of(v1, v2, v3, a.slope);
+        const double sp = slope_of(v2, v3, v4, a.slope);
+        const double F0 = species_face(v1 + 0.5 * sm, v2 - 0.5 * s0, fy[0]);
+        const double F1 = species_face(v2 + 0.5 * s0, v3 - 0.5 * sp, fy[1]);
+        As -= (F1 - F0) * idy;
+      }
+      {
+        const double u2 = (U + (i64)c * Z)[p2 + col];
+        const double d1 = slope_of(Uk[t], Uk1[t], u2, a.slope);
+        const double F1 = species_face(Uk[t] + 0.5 * dUk[t], Uk1[t] - 0.5 * d1, fz);
+        As -= (F1 - Fm[t]) * idz;
+        Fm[t] = F1;
+        Uk[t] = Uk1[t];
+        Uk1[t] = u2;
+        dUk[t] = d1;
+      }
+      if (active && ok) (a.A + (i64)c * Z)[pk + col] = As;
+    }
+    __syncthreads();
+  }
+}
+#endif
+
 // ------------------------------------------------------------ reactions
 struct VecX {
   double v[SDC_NX];
@@ -423,13 +627,6 @@ __device__ __forceinline__ constexpr int react_index(int c) {
   return c == 1 + SDC_DIM ? SDC_NX - 1 : (c >= SDC_NH ? c - SDC_NH : -1);
 }
 
-// rhs[c] = v for a run-time c without dynamic register indexing
-__device__ __forceinline__ void rhs_store(double* rhs, int c, double v) {
-#pragma unroll
-  for (int q = 0; q < SDC_NC; ++q)
-    if (q == c) rhs[q] = v;
-}
-
 template <class MT, int KIND>
 __device__ __forceinline__ void transition_body(const TransArgs& a) {
   const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
@@ -443,7 +640,7 @@ __device__ __forceinline__ void transition_body(const TransArgs& a) {
 #pragma unroll
       for (int c = 0; c < SDC_NC; ++c) rhs[c] = fma(a.dtm, a.Am[(i64)c * Z + z], a.Um[(i64)c * Z + z]);
     } else if (KIND == KIND_NODE0) {
-#pragma unroll 1
+#pragma unroll
       for (int c = 0; c < SDC_NC; ++c) {
         const int ri = c == 1 + SDC_DIM ? SDC_NX - 1 : (c >= SDC_NH ? c - SDC_NH : -1);
         double f[SDC_NNODES];
@@ -457,7 +654,7 @@ __device__ __forceinline__ void transition_body(const TransArgs& a) {
         for (int j = 0; j <= SDC_M; ++j) i0 = fma(a.S[0][j], f[j], i0);
         double r = fma(a.dt, i0, a.Um[(i64)c * Z + z]);
         if (ri >= 0) r = fma(-a.dtm, a.Rold[1][(i64)ri * Z + z], r);
-        rhs_store(rhs, c, r);
+        rhs[c] = r;
 #pragma unroll
         for (int mm = 1; mm < SDC_M; ++mm) {
           double im = 0.0;

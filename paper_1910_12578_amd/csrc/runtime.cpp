@@ -328,7 +328,7 @@ struct sdc_handle_s {
   std::vector<double> tau;
   std::vector<std::vector<double>> S;
   hipModule_t mod = nullptr;
-  hipFunction_t f_advect = nullptr, f_source = nullptr, f_solve = nullptr, f_first = nullptr,
+  hipFunction_t f_advect = nullptr, f_advect3d = nullptr, f_source = nullptr, f_solve = nullptr, f_first = nullptr,
                 f_node0 = nullptr, f_later = nullptr, f_fill = nullptr;
   void* d_params = nullptr;
   unsigned long long* d_stats = nullptr;
@@ -362,7 +362,7 @@ int fail(sdc_handle h, int code, const std::string& msg) {
   } while (0)
 
 int kind_of(const sdc_handle h, hipFunction_t f) {
-  if (f == h->f_advect) return SDC_K_ADVECT;
+  if (f == h->f_advect || f == h->f_advect3d) return SDC_K_ADVECT;
   if (f == h->f_source) return SDC_K_SOURCE;
   if (f == h->f_solve) return SDC_K_SOLVE;
   if (f == h->f_first) return SDC_K_TRANSITION_FIRST;
@@ -429,6 +429,12 @@ int advect(sdc_handle h, const double* U, double* A, hipStream_t s) {
   a.gamma = c.gamma;
   a.alpha = c.alpha;
   a.slope = c.slope;
+  if (c.dim == 3 && h->f_advect3d) {
+    // z-marching kernel: one 256-thread block per 64 x 4 column tile and z chunk
+    const int spg = h->ns < 5 ? h->ns : 5, ngrp = (h->ns + spg - 1) / spg;
+    const int64_t nb = ((c.n[0] + 63) / 64) * ((c.n[1] + 3) / 4) * ((c.n[2] + 31) / 32) * ngrp;
+    return launch(h, h->f_advect3d, nb * kBlock, &a, s);
+  }
   return launch(h, h->f_advect, h->P.Z, &a, s);
 }
 
@@ -585,6 +591,13 @@ int sdc_init(const sdc_config* cfg, const sdc_network* net, sdc_handle* out) {
   for (auto& fn : fns) {
     e = hipModuleGetFunction(fn.f, h->mod, fn.name);
     if (e != hipSuccess) return bail(SDC_ERR_HIP, std::string("missing kernel ") + fn.name);
+  }
+  // SDC_ADVECT3D=1 selects the z-marching 3D kernel (needs 32-bit offsets
+  // inside one component array); the zone-per-thread kernel is the default
+  const char* ev = std::getenv("SDC_ADVECT3D");
+  if (h->P.cfg.dim == 3 && h->P.Z < (int64_t(1) << 28) && ev && ev[0] == '1') {
+    e = hipModuleGetFunction(&h->f_advect3d, h->mod, "sdc_advect3d");
+    if (e != hipSuccess) return bail(SDC_ERR_HIP, "missing kernel sdc_advect3d");
   }
   const std::vector<double> img = params_image(h->P, h->nra);
   e = hipMalloc(&h->d_params, img.size() * sizeof(double));
