@@ -103,6 +103,16 @@ typedef struct {
   double newton_tol;       /* stop when max_i |delta_i| / s_i <= tol (s = rho, |b_e|) */
   int32_t newton_maxiter;  /* >= 1 */
   double pivot_threshold;  /* tau: a pivot below tau * column max takes the pivoted path */
+  /* Batched boxes: nbox > 0 replaces the single grid by nbox independent
+   * periodic boxes sharing dx (n[] is ignored).  box_n (host, copied) holds
+   * [nbox][3] extents (x, y, z; entries beyond dim ignored).  The state is the
+   * concatenation of the boxes in order, each box x-fastest, still SoA
+   * [component][zone] over all zones. */
+  int32_t nbox;
+  const int64_t* box_n;
+  /* 1: sdc_step replays one captured HIP graph per step (per buffer-rotation
+   * phase); 0 (default): plain launches.  Profiling forces launches. */
+  int32_t graph;
 } sdc_config;
 
 /*
@@ -121,7 +131,8 @@ typedef struct {
 } sdc_nodes;
 
 /* Fill `cfg` with defaults: 3 nodes, K = 4, FP64, MC slopes, local Rusanov
- * speed, gamma 1.4, tol 1e-13, maxiter 50, pivot threshold 0.1. */
+ * speed, gamma 1.4, tol 1e-13, maxiter 50, pivot threshold 0.1, no boxes,
+ * plain launches. */
 int sdc_config_default(sdc_config* cfg);
 
 /*
@@ -193,6 +204,22 @@ int sdc_stats_reset(sdc_handle h, void* stream);
  * the handle's last stream before any later work. */
 int sdc_set_params(sdc_handle h, const double* lnA, const double* E);
 
+/*
+ * Adjoint of one step (reverse mode): given U^n and the adjoint Ubar^{n+1} of
+ * the step's output U^{n+1}, writes Ubar^n = (dU^{n+1}/dU^n)^T Ubar^{n+1} and
+ * accumulates thetabar[0..nreact) += d/dlnA_r, thetabar[nreact..2 nreact) +=
+ * d/dE_r of (Ubar^{n+1} . U^{n+1}).  The step is replayed forward from U^n
+ * (node states of every iteration kept in handle-owned workspace, allocated
+ * on first use), then every implicit reaction solve is differentiated with
+ * the implicit-function theorem at its converged root and the quadrature and
+ * advective terms are transposed.  Requires a single grid and, with
+ * advection on, the smooth mode (slope 0, frozen alpha > 0); otherwise
+ * SDC_ERR_UNSUPPORTED.  U_n, Ubar_np1, Ubar_n: [n_c][Z] device, distinct;
+ * thetabar: device [2 nreact].  Deterministic: no floating-point atomics.
+ */
+int sdc_step_adjoint(sdc_handle h, double dt, const double* U_n, const double* Ubar_np1, double* Ubar_n,
+                     double* thetabar, void* stream);
+
 /* Kernel kinds for sdc_profile_read. */
 #define SDC_K_ADVECT 0
 #define SDC_K_SOURCE 1
@@ -201,7 +228,8 @@ int sdc_set_params(sdc_handle h, const double* lnA, const double* E);
 #define SDC_K_TRANSITION_NODE0 4
 #define SDC_K_TRANSITION_LATER 5
 #define SDC_K_FILL 6
-#define SDC_NKINDS 7
+#define SDC_K_ADJOINT 7  /* every kernel of the adjoint pass */
+#define SDC_NKINDS 8
 
 /*
  * Per-kernel timing: while enabled, every launch is bracketed by HIP events

@@ -23,8 +23,10 @@ ERRORS = {1: "SDC_ERR_ARG", 2: "SDC_ERR_HIP", 3: "SDC_ERR_NOMEM", 4: "SDC_ERR_NE
 EXPORTS = ("sdc_config_default", "sdc_init", "sdc_destroy", "sdc_last_error", "sdc_sizes",
            "sdc_advective_term", "sdc_source", "sdc_reaction_solve", "sdc_sweep", "sdc_step",
            "sdc_stats", "sdc_stats_reset", "sdc_set_params", "sdc_compile_only",
-           "sdc_generated_source", "sdc_profile_enable", "sdc_profile_read", "sdc_cost_model")
-KINDS = ("advect", "source", "solve", "transition_first", "transition_node0", "transition_later", "fill")
+           "sdc_generated_source", "sdc_profile_enable", "sdc_profile_read", "sdc_cost_model",
+           "sdc_step_adjoint")
+KINDS = ("advect", "source", "solve", "transition_first", "transition_node0", "transition_later", "fill",
+         "adjoint")
 
 
 class SDCError(RuntimeError):
@@ -44,7 +46,8 @@ class Config(ctypes.Structure):
                 ("n_nodes", c_int32), ("n_iters", c_int32), ("precision", c_int32),
                 ("advection", c_int32), ("slope", c_int32), ("alpha", c_double),
                 ("newton_tol", c_double), ("newton_maxiter", c_int32),
-                ("pivot_threshold", c_double)]
+                ("pivot_threshold", c_double), ("nbox", c_int32), ("box_n", POINTER(c_int64)),
+                ("graph", c_int32)]
 
 
 class Nodes(ctypes.Structure):
@@ -86,6 +89,7 @@ def lib():
         L.sdc_profile_enable.argtypes = [c_void_p, c_int32]
         L.sdc_profile_read.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int64)]
         L.sdc_cost_model.argtypes = [c_void_p, POINTER(c_int64)]
+        L.sdc_step_adjoint.argtypes = [c_void_p, c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype or c_int
         _lib = L
@@ -113,16 +117,22 @@ def make_network(net):
 
 
 def make_config(cfg):
+    """ctypes config struct; a box table, if any, is kept alive on the struct."""
     c = Config()
     lib().sdc_config_default(byref(c))
     c.dim = int(cfg["dim"])
+    if cfg.get("box_n") is not None:
+        boxes = np.ascontiguousarray(cfg["box_n"], dtype=np.int64).reshape(-1, 3)
+        c.nbox = boxes.shape[0]
+        c.box_n = boxes.ctypes.data_as(POINTER(c_int64))
+        c._keep_boxes = boxes
     for d in range(3):
         c.n[d] = int(cfg["n"][d]) if d < len(cfg["n"]) else 1
         c.dx[d] = float(cfg["dx"][d]) if d < len(cfg["dx"]) else 1.0
     for key in ("gamma", "alpha", "newton_tol", "pivot_threshold"):
         if key in cfg:
             setattr(c, key, float(cfg[key]))
-    for key in ("n_nodes", "n_iters", "precision", "advection", "slope", "newton_maxiter"):
+    for key in ("n_nodes", "n_iters", "precision", "advection", "slope", "newton_maxiter", "graph"):
         if key in cfg:
             setattr(c, key, int(cfg[key]))
     return c
@@ -130,10 +140,12 @@ def make_config(cfg):
 
 def config_from_workload(w, **over):
     """Config dict of an `sdc_inputs.workload` record (x-first extents)."""
-    cfg = dict(dim=w["dim"], n=tuple(w["shape"]), dx=tuple(w["dx"]), gamma=w["gamma"],
+    cfg = dict(dim=w["dim"], n=tuple(w["shape"] or ()), dx=tuple(w["dx"]), gamma=w["gamma"],
                n_nodes=w["n_nodes"], n_iters=w["n_iters"], precision=SDC_FP64, advection=1,
                slope=w["slope"], alpha=w["alpha"], newton_tol=w["newton_tol"],
                newton_maxiter=w["newton_maxiter"])
+    if w.get("box_n") is not None:
+        cfg["box_n"] = w["box_n"]
     cfg.update(over)
     return cfg
 
@@ -269,6 +281,19 @@ class SDC:
         _check(lib().sdc_step(self._h, float(dt), int(nsteps), self._ptr(U, self.ncomp), byref(n),
                               self._stream(stream)), self._h)
         return U
+
+    def step_adjoint(self, dt, U_n, Ubar_np1, Ubar_n=None, thetabar=None, stream=None):
+        """One step backward: Ubar_n = (dU^{n+1}/dU^n)^T Ubar_np1; thetabar += parameter adjoints."""
+        import torch
+        Ubar_n = self.empty(self.ncomp) if Ubar_n is None else Ubar_n
+        if thetabar is None:
+            thetabar = torch.zeros(2 * max(self.nreact, 1), dtype=torch.float64, device="cuda")
+        if thetabar.numel() < 2 * self.nreact or not thetabar.is_cuda or thetabar.dtype != torch.float64:
+            raise ValueError("thetabar must be a float64 CUDA tensor with 2 * nreact entries")
+        _check(lib().sdc_step_adjoint(self._h, float(dt), self._ptr(U_n, self.ncomp), self._ptr(Ubar_np1, self.ncomp),
+                                      self._ptr(Ubar_n, self.ncomp), c_void_p(thetabar.data_ptr()),
+                                      self._stream(stream)), self._h)
+        return Ubar_n, thetabar
 
     def stats(self):
         out = (c_int64 * NSTATS)()

@@ -21,6 +21,12 @@ typedef struct {
   double gamma;
   double alpha;   // > 0: frozen Rusanov speed
   int slope;      // 0 = central, 1 = MC
+  // batched boxes (nbox > 0): zone offsets [nbox+1], extents [nbox][3] and
+  // the box holding each 256-zone block's first zone [nblocks]
+  int nbox;
+  const sdc_i64* box_off;
+  const int* box_ext;
+  const int* blk_box;
 } AdvArgs;
 
 typedef struct {
@@ -71,5 +77,66 @@ typedef struct {
   sdc_i64 n;
   double v;
 } FillArgs;
+
+// Adjoint of A (smooth mode: central slopes, frozen Rusanov speed):
+// Ubar += (dA/dU)^T Abar, evaluated at U, gather form.
+typedef struct {
+  const double* U;
+  const double* Abar;
+  double* Ubar;
+  sdc_i64 Z;
+  int n[3];
+  double idx[3];
+  double gamma;
+  double alpha;
+} AdvVjpArgs;
+
+// Adjoint of one node transition m -> m+1 at iteration k -> k+1, with the
+// transposes of its right-hand side assembly fused in.
+typedef struct {
+  sdc_i64 Z;
+  int m, M, first;
+  double dt, dtm;
+  double S[SDC_MAXNODE - 1][SDC_MAXNODE];
+  double dtj[SDC_MAXNODE - 1];
+  const double* Uout;      // forward state U^{m+1,(k+1)}
+  const double* Uoutbar;   // its adjoint (complete)
+  const double* Routbar;   // adjoint of R^{m+1,(k+1)} (complete)
+  double* Umbar;           // += rhs bar: adjoint of U^{m,(k+1)} (or of U^n for m = 0)
+  double* Ambar;           // += dt_m rhs bar: adjoint of A^{m,(k+1)} (m >= 1)
+  double* Aoldbar[SDC_MAXNODE];  // adjoints of A^{j,(k)} (all node 0 when first)
+  double* Roldbar[SDC_MAXNODE];  // adjoints of R^{j,(k)}
+  const void* P;
+  double gm1;
+  double tau;
+  double* theta_part;      // [nblocks][2 * nreact] partial parameter adjoints
+} TransAdjArgs;
+
+// Adjoint of R(U) at U: Ubar += (dR/dU)^T Rbar, parameter partials.
+typedef struct {
+  sdc_i64 Z;
+  const double* U;
+  const double* Rbar;
+  double* Ubar;
+  const void* P;
+  double gm1;
+  double* theta_part;
+} SourceVjpArgs;
+
+// Sum the per-block parameter partials in block order into thetabar (+=).
+typedef struct {
+  const double* part;
+  sdc_i64 nblocks;
+  int nparam;
+  double* thetabar;
+} ThetaReduceArgs;
+
+// y += a * x over n doubles
+typedef struct {
+  double* y;
+  const double* x;
+  double a;
+  sdc_i64 n;
+} AxpyArgs;
 
 #endif

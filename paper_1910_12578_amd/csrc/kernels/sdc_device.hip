@@ -100,14 +100,26 @@ extern "C" __global__ __launch_bounds__(256) void sdc_advect(AdvArgs a) {
   const unsigned b = xcd_block(blockIdx.x, gridDim.x);
   const i64 z = (i64)b * blockDim.x + threadIdx.x;
   if (z >= a.Z) return;
+  // grid (or box) extents and the zone's coordinates inside it; with batched
+  // boxes every box is its own periodic grid, so neighbours stay in the box
+  int n[3] = {a.n[0], a.n[1], a.n[2]};
+  i64 local = z;
+  if (a.nbox > 0) {
+    int bx = a.blk_box[b];
+    while (z >= a.box_off[bx + 1]) ++bx;  // a block may straddle boxes
+    n[0] = a.box_ext[3 * bx];
+    n[1] = a.box_ext[3 * bx + 1];
+    n[2] = a.box_ext[3 * bx + 2];
+    local = z - a.box_off[bx];
+  }
   int c3[3] = {0, 0, 0};
   {
-    i64 t = z;
-    c3[0] = (int)(t % a.n[0]);
-    t /= a.n[0];
+    i64 t = local;
+    c3[0] = (int)(t % n[0]);
+    t /= n[0];
     if (SDC_DIM > 1) {
-      c3[1] = (int)(t % a.n[1]);
-      t /= a.n[1];
+      c3[1] = (int)(t % n[1]);
+      t /= n[1];
     }
     if (SDC_DIM > 2) c3[2] = (int)t;
   }
@@ -118,7 +130,7 @@ extern "C" __global__ __launch_bounds__(256) void sdc_advect(AdvArgs a) {
     i64 stride = 1;
 #pragma unroll
     for (int d = 0; d < SDC_DIM; ++d) {
-      const int nd = a.n[d], cd = c3[d];
+      const int nd = n[d], cd = c3[d];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int sh = s < 2 ? s - 2 : s - 1;
@@ -406,6 +418,36 @@ struct DenseResult {
   int it;  // iteration count at exit, or -1
 };
 
+// Dense Newton matrix M = I - dt_m dR/dx (row-major) and r = -(x - dt_m R - b),
+// assembled with rolled loops over the topology tables (scratch resident).
+__device__ __forceinline__ void dense_newton_matrix(const double* x, const double* b, double irho, double dtm,
+                                                    ParamPtr P, double gm1, double* M, double* r) {
+  const int e = SDC_NX - 1;
+  for (int i = 0; i < SDC_NX * SDC_NX; ++i) M[i] = 0.0;
+  for (int i = 0; i < SDC_NX; ++i) {
+    M[i * SDC_NX + i] = 1.0;
+    r[i] = b[i] - x[i];
+  }
+  const double T = gm1 * x[e] * irho, lnT = log(T), invT = 1.0 / T, dTdxe = gm1 * irho;
+  for (int q = 0; q < SDC_NR; ++q) {
+    const double k = exp(fma(P->b[q], lnT, P->lnA[q]) - P->E[q] * invT);
+    const int a = kRxA[q], c = kRxC[q];
+    const double mono = c < 0 ? x[a] : x[a] * x[c];
+    const double v = k * mono;
+    const double da = c < 0 ? k : (a == c ? 2.0 * k * x[a] : k * x[c]);
+    const double dc = c < 0 ? 0.0 : (a == c ? 0.0 : k * x[a]);
+    const double de = v * fma(P->E[q], invT * invT, P->b[q] * invT) * dTdxe;
+    for (int s = 0; s <= kRxN[q]; ++s) {
+      const int i = s < kRxN[q] ? kRxSp[q][s] : e;
+      const double w = (s < kRxN[q] ? kRxS[q][s] : P->Q[q]) * dtm;  // row weight
+      r[i] = fma(w, v, r[i]);
+      M[i * SDC_NX + a] -= w * da;
+      if (c >= 0) M[i * SDC_NX + c] -= w * dc;
+      M[i * SDC_NX + e] -= w * de;
+    }
+  }
+}
+
 // Newton with a dense, partially pivoted LU of M = I - dt_m dR/dx, continued
 // from iterate x after `it0` iterations.  Used only for zones whose fixed-
 // order factorisation met a pivot below tau times its column maximum.  It is
@@ -427,29 +469,7 @@ __device__ __attribute__((noinline)) DenseResult dense_newton(VecX xv, VecX bv, 
   for (int it = it0; it <= maxiter; ++it) {
     double M[SDC_NX * SDC_NX];
     double r[SDC_NX];
-    for (int i = 0; i < SDC_NX * SDC_NX; ++i) M[i] = 0.0;
-    for (int i = 0; i < SDC_NX; ++i) {
-      M[i * SDC_NX + i] = 1.0;
-      r[i] = b[i] - x[i];  // -G without the reaction terms
-    }
-    const double T = gm1 * x[e] * irho, lnT = log(T), invT = 1.0 / T, dTdxe = gm1 * irho;
-    for (int q = 0; q < SDC_NR; ++q) {
-      const double k = exp(fma(P->b[q], lnT, P->lnA[q]) - P->E[q] * invT);
-      const int a = kRxA[q], c = kRxC[q];
-      const double mono = c < 0 ? x[a] : x[a] * x[c];
-      const double v = k * mono;
-      const double da = c < 0 ? k : (a == c ? 2.0 * k * x[a] : k * x[c]);
-      const double dc = c < 0 ? 0.0 : (a == c ? 0.0 : k * x[a]);
-      const double de = v * fma(P->E[q], invT * invT, P->b[q] * invT) * dTdxe;
-      for (int s = 0; s <= kRxN[q]; ++s) {
-        const int i = s < kRxN[q] ? kRxSp[q][s] : e;
-        const double w = (s < kRxN[q] ? kRxS[q][s] : P->Q[q]) * dtm;  // row weight
-        r[i] = fma(w, v, r[i]);
-        M[i * SDC_NX + a] -= w * da;
-        if (c >= 0) M[i * SDC_NX + c] -= w * dc;
-        M[i * SDC_NX + e] -= w * de;
-      }
-    }
+    dense_newton_matrix(x, b, irho, dtm, P, gm1, M, r);
     for (int k = 0; k < SDC_NX; ++k) {
       int p = k;
       double best = fabs(M[k * SDC_NX + k]);
@@ -725,4 +745,327 @@ extern "C" __global__ __launch_bounds__(256) void sdc_transition_later(TransArgs
 extern "C" __global__ __launch_bounds__(256) void sdc_fill(FillArgs a) {
   const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < a.n) a.p[i] = a.v;
+}
+
+// ====================================================================== adjoint
+// Reverse mode of the SDC step for gradients of a scalar objective with respect
+// to the state and the rate parameters theta = (lnA_r, E_r).  Each implicit
+// reaction solve is differentiated with the implicit-function theorem at its
+// converged root: with M = I - dt_m dR/dx, mu = M^{-T} xbar gives bbar = mu and
+// the parameter and density adjoints dt_m (dR/dtheta)^T mu, dt_m (dR/drho)^T mu.
+// The advective term is differentiated in its smooth mode (central slopes,
+// frozen Rusanov speed), where it is a differentiable function of U.
+
+// (dF/dU)^T w for the Euler flux plus passive species in direction d at state W.
+__device__ __forceinline__ void flux_jt(const double* W, int d, double gamma, const double* w, double* v) {
+  const double g = gamma - 1.0;
+  const double rho = W[0], ir = 1.0 / rho;
+  double u[SDC_DIM], q2 = 0.0, wmu = 0.0;
+#pragma unroll
+  for (int k = 0; k < SDC_DIM; ++k) {
+    u[k] = W[1 + k] * ir;
+    q2 = fma(u[k], u[k], q2);
+    wmu = fma(w[1 + k], u[k], wmu);
+  }
+  const double E = W[1 + SDC_DIM];
+  const double p = g * (E - 0.5 * rho * q2);
+  const double H = (E + p) * ir;
+  const double ud = u[d], wmd = w[1 + d], wE = w[1 + SDC_DIM];
+  double wsX = 0.0;
+#pragma unroll
+  for (int s = 0; s < SDC_NS; ++s) wsX = fma(w[SDC_NH + s], W[SDC_NH + s] * ir, wsX);
+  const double hq = 0.5 * g * q2;
+  v[0] = -ud * wmu + wmd * hq + wE * ud * (hq - H) - ud * wsX;
+#pragma unroll
+  for (int k = 0; k < SDC_DIM; ++k) {
+    double t = w[1 + k] * ud - g * u[k] * wmd - g * u[k] * ud * wE;
+    if (k == d) t += w[0] + wmu + H * wE + wsX;
+    v[1 + k] = t;
+  }
+  v[1 + SDC_DIM] = g * wmd + (1.0 + g) * ud * wE;
+#pragma unroll
+  for (int s = 0; s < SDC_NS; ++s) v[SDC_NH + s] = ud * w[SDC_NH + s];
+}
+
+extern "C" __global__ __launch_bounds__(256) void sdc_advect_vjp(AdvVjpArgs a) {
+  const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= a.Z) return;
+  int c3[3] = {0, 0, 0};
+  {
+    i64 t = z;
+    c3[0] = (int)(t % a.n[0]);
+    t /= a.n[0];
+    if (SDC_DIM > 1) {
+      c3[1] = (int)(t % a.n[1]);
+      t /= a.n[1];
+    }
+    if (SDC_DIM > 2) c3[2] = (int)t;
+  }
+  double ub[SDC_NC];
+#pragma unroll
+  for (int c = 0; c < SDC_NC; ++c) ub[c] = 0.0;
+  i64 stride = 1;
+  for (int d = 0; d < SDC_DIM; ++d) {
+    const int nd = a.n[d], cd = c3[d];
+    i64 off[7];  // zones j-3 .. j+3 along d
+    for (int s = -3; s <= 3; ++s) {
+      int cc = cd + s;
+      while (cc < 0) cc += nd;
+      while (cc >= nd) cc -= nd;
+      off[s + 3] = z + (i64)(cc - cd) * stride;
+    }
+    // faces i+1/2 for i = j-2 .. j+1 (r = i - j = -2 .. 1)
+    for (int r = -2; r <= 1; ++r) {
+      const double cL = r == 1 ? -0.25 : (r == 0 ? 1.0 : (r == -1 ? 0.25 : 0.0));
+      const double cR = r == 0 ? 0.25 : (r == -1 ? 1.0 : (r == -2 ? -0.25 : 0.0));
+      const i64 im1 = off[r + 2], i0 = off[r + 3], ip1 = off[r + 4], ip2 = off[r + 5];
+      double Fb[SDC_NC], W[SDC_NC], v[SDC_NC];
+#pragma unroll
+      for (int c = 0; c < SDC_NC; ++c) Fb[c] = (a.Abar[(i64)c * a.Z + ip1] - a.Abar[(i64)c * a.Z + i0]) * a.idx[d];
+      if (cL != 0.0) {
+#pragma unroll
+        for (int c = 0; c < SDC_NC; ++c) {
+          const double* Uc = a.U + (i64)c * a.Z;
+          W[c] = Uc[i0] + 0.25 * (Uc[ip1] - Uc[im1]);
+        }
+        flux_jt(W, d, a.gamma, Fb, v);
+#pragma unroll
+        for (int c = 0; c < SDC_NC; ++c) ub[c] = fma(cL, 0.5 * v[c] + 0.5 * a.alpha * Fb[c], ub[c]);
+      }
+      if (cR != 0.0) {
+#pragma unroll
+        for (int c = 0; c < SDC_NC; ++c) {
+          const double* Uc = a.U + (i64)c * a.Z;
+          W[c] = Uc[ip1] - 0.25 * (Uc[ip2] - Uc[i0]);
+        }
+        flux_jt(W, d, a.gamma, Fb, v);
+#pragma unroll
+        for (int c = 0; c < SDC_NC; ++c) ub[c] = fma(cR, 0.5 * v[c] - 0.5 * a.alpha * Fb[c], ub[c]);
+      }
+    }
+    stride *= nd;
+  }
+#pragma unroll
+  for (int c = 0; c < SDC_NC; ++c) a.Ubar[(i64)c * a.Z + z] += ub[c];
+}
+
+// Dense transposed solve M^T y = c with a partially pivoted LU of M (used when
+// the fixed-order factorisation meets a small pivot).
+__device__ __attribute__((noinline)) VecX dense_solve_t(VecX xv, VecX cv, double irho, double dtm, ParamPtr P,
+                                                        double gm1) {
+  double x[SDC_NX], M[SDC_NX * SDC_NX], r[SDC_NX], y[SDC_NX];
+  int piv[SDC_NX];
+  for (int i = 0; i < SDC_NX; ++i) x[i] = xv.v[i];
+  dense_newton_matrix(x, x, irho, dtm, P, gm1, M, r);
+  for (int k = 0; k < SDC_NX; ++k) {
+    int p = k;
+    double best = fabs(M[k * SDC_NX + k]);
+    for (int i = k + 1; i < SDC_NX; ++i)
+      if (fabs(M[i * SDC_NX + k]) > best) {
+        best = fabs(M[i * SDC_NX + k]);
+        p = i;
+      }
+    piv[k] = p;
+    if (p != k)
+      for (int j = 0; j < SDC_NX; ++j) {
+        const double t = M[k * SDC_NX + j];
+        M[k * SDC_NX + j] = M[p * SDC_NX + j];
+        M[p * SDC_NX + j] = t;
+      }
+    const double inv = 1.0 / M[k * SDC_NX + k];
+    for (int i = k + 1; i < SDC_NX; ++i) {
+      const double l = M[i * SDC_NX + k] * inv;
+      M[i * SDC_NX + k] = l;
+      for (int j = k + 1; j < SDC_NX; ++j) M[i * SDC_NX + j] = fma(-l, M[k * SDC_NX + j], M[i * SDC_NX + j]);
+    }
+  }
+  // P M = L U  =>  M^T = U^T L^T P:  U^T w = c, L^T v = w, y = P^T v
+  for (int k = 0; k < SDC_NX; ++k) {
+    double s = cv.v[k];
+    for (int j = 0; j < k; ++j) s = fma(-M[j * SDC_NX + k], y[j], s);
+    y[k] = s / M[k * SDC_NX + k];
+  }
+  for (int k = SDC_NX - 1; k >= 0; --k) {
+    double s = y[k];
+    for (int i = k + 1; i < SDC_NX; ++i) s = fma(-M[i * SDC_NX + k], y[i], s);
+    y[k] = s;
+  }
+  for (int k = SDC_NX - 1; k >= 0; --k)
+    if (piv[k] != k) {
+      const double t = y[k];
+      y[k] = y[piv[k]];
+      y[piv[k]] = t;
+    }
+  VecX out;
+  for (int i = 0; i < SDC_NX; ++i) out.v[i] = y[i];
+  return out;
+}
+
+// Deterministic block sum of the per-zone parameter adjoints into part[block][*].
+__device__ __forceinline__ void theta_block_sum(double* gl, double* gE, double* part) {
+  __shared__ double sh[4];
+  for (int p = 0; p < 2 * SDC_NR; ++p) {
+    double v = p < SDC_NR ? gl[p] : gE[p - SDC_NR];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+      part[(i64)blockIdx.x * (2 * SDC_NR) + p] = t;
+    }
+    __syncthreads();
+  }
+}
+
+template <int FIRST>
+__device__ __forceinline__ void transition_adjoint_body(const TransAdjArgs& a) {
+  const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = z < a.Z;
+  ParamPtr P = (ParamPtr)a.P;
+  double gl[SDC_NRA], gE[SDC_NRA];
+#pragma unroll
+  for (int r = 0; r < SDC_NRA; ++r) gl[r] = gE[r] = 0.0;
+  if (valid) {
+    const i64 Z = a.Z;
+    const double rho = a.Uout[z];
+    const double irho = 1.0 / rho;
+    double mom[SDC_DIM], ke = 0.0;
+#pragma unroll
+    for (int d = 0; d < SDC_DIM; ++d) {
+      mom[d] = a.Uout[(i64)(1 + d) * Z + z];
+      ke = fma(mom[d], mom[d], ke);
+    }
+    ke = 0.5 * ke * irho;
+    double x[SDC_NX], w[SDC_NX], xb[SDC_NX], mu[SDC_NX];
+#pragma unroll
+    for (int s = 0; s < SDC_NS; ++s) x[s] = a.Uout[(i64)(SDC_NH + s) * Z + z];
+    x[SDC_NX - 1] = a.Uout[(i64)(1 + SDC_DIM) * Z + z] - ke;
+#pragma unroll
+    for (int i = 0; i < SDC_NX; ++i) w[i] = a.Routbar[(i64)i * Z + z];
+    // R^{m+1} = R(x; rho): its adjoint feeds x, rho and theta
+    double rhob;
+    net_vjp(x, irho, P, a.gm1, w, xb, &rhob, gl, gE);
+#pragma unroll
+    for (int s = 0; s < SDC_NS; ++s) mu[s] = a.Uoutbar[(i64)(SDC_NH + s) * Z + z] + xb[s];
+    const double UbE = a.Uoutbar[(i64)(1 + SDC_DIM) * Z + z];
+    mu[SDC_NX - 1] = UbE + xb[SDC_NX - 1];
+    rhob += a.Uoutbar[z];
+    // implicit solve: mu = M^{-T} xbar at the converged root
+    {
+      double G[SDC_NX], Mtx[SDC_NNZ];
+      net_residual_matrix<double>(x, x, irho, a.dtm, P, a.gm1, G, Mtx);
+      if (net_lu<double>(Mtx, a.tau)) {
+        net_solve_t<double>(Mtx, mu);
+      } else {
+        VecX xv, cv;
+#pragma unroll
+        for (int i = 0; i < SDC_NX; ++i) {
+          xv.v[i] = x[i];
+          cv.v[i] = mu[i];
+        }
+        const VecX y = dense_solve_t(xv, cv, irho, a.dtm, P, a.gm1);
+#pragma unroll
+        for (int i = 0; i < SDC_NX; ++i) mu[i] = y.v[i];
+      }
+    }
+    // parameters and density through the solve: dt_m (dR/d.)^T mu
+    {
+      double wm[SDC_NX], xb2[SDC_NX], rhob2;
+#pragma unroll
+      for (int i = 0; i < SDC_NX; ++i) wm[i] = a.dtm * mu[i];
+      net_vjp(x, irho, P, a.gm1, wm, xb2, &rhob2, gl, gE);
+      rhob += rhob2;
+    }
+    // bbar = mu; rho E = x_e + KE and b_e = rhs_E - KE
+    const double keb = UbE - mu[SDC_NX - 1];
+    double rb[SDC_NC];
+    rb[0] = rhob - keb * ke * irho;
+#pragma unroll
+    for (int d = 0; d < SDC_DIM; ++d) rb[1 + d] = a.Uoutbar[(i64)(1 + d) * Z + z] + keb * mom[d] * irho;
+    rb[1 + SDC_DIM] = mu[SDC_NX - 1];
+#pragma unroll
+    for (int s = 0; s < SDC_NS; ++s) rb[SDC_NH + s] = mu[s];
+    // transposes of the right-hand side assembly
+#pragma unroll
+    for (int c = 0; c < SDC_NC; ++c) {
+      const i64 o = (i64)c * Z + z;
+      const int ri = c == 1 + SDC_DIM ? SDC_NX - 1 : (c >= SDC_NH ? c - SDC_NH : -1);
+      a.Umbar[o] += rb[c];
+      if (a.Ambar) a.Ambar[o] += a.dtm * rb[c];
+      if (!FIRST) {
+        for (int j = 0; j <= a.M; ++j) {
+          const double f = a.dt * a.S[a.m][j] * rb[c];
+          a.Aoldbar[j][o] += f;
+          if (ri >= 0) a.Roldbar[j][(i64)ri * Z + z] += f;
+        }
+        if (a.m >= 1) a.Aoldbar[a.m][o] -= a.dtm * rb[c];
+        if (ri >= 0) a.Roldbar[a.m + 1][(i64)ri * Z + z] -= a.dtm * rb[c];
+      }
+    }
+  }
+  theta_block_sum(gl, gE, a.theta_part);
+}
+
+extern "C" __global__ __launch_bounds__(256) void sdc_transition_adjoint_first(TransAdjArgs a) {
+  transition_adjoint_body<1>(a);
+}
+extern "C" __global__ __launch_bounds__(256) void sdc_transition_adjoint(TransAdjArgs a) {
+  transition_adjoint_body<0>(a);
+}
+
+// Ubar += (dR(U)/dU)^T Rbar at U, with x = (rho X, rho E - KE); parameter partials.
+extern "C" __global__ __launch_bounds__(256) void sdc_source_vjp(SourceVjpArgs a) {
+  const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = z < a.Z;
+  ParamPtr P = (ParamPtr)a.P;
+  double gl[SDC_NRA], gE[SDC_NRA];
+#pragma unroll
+  for (int r = 0; r < SDC_NRA; ++r) gl[r] = gE[r] = 0.0;
+  if (valid) {
+    const i64 Z = a.Z;
+    const double rho = a.U[z], irho = 1.0 / rho;
+    double mom[SDC_DIM], ke = 0.0;
+#pragma unroll
+    for (int d = 0; d < SDC_DIM; ++d) {
+      mom[d] = a.U[(i64)(1 + d) * Z + z];
+      ke = fma(mom[d], mom[d], ke);
+    }
+    ke = 0.5 * ke * irho;
+    double x[SDC_NX], w[SDC_NX], xb[SDC_NX], rhob;
+#pragma unroll
+    for (int s = 0; s < SDC_NS; ++s) x[s] = a.U[(i64)(SDC_NH + s) * Z + z];
+    x[SDC_NX - 1] = a.U[(i64)(1 + SDC_DIM) * Z + z] - ke;
+#pragma unroll
+    for (int i = 0; i < SDC_NX; ++i) w[i] = a.Rbar[(i64)i * Z + z];
+    net_vjp(x, irho, P, a.gm1, w, xb, &rhob, gl, gE);
+    const double keb = -xb[SDC_NX - 1];
+    a.Ubar[z] += rhob - keb * ke * irho;
+#pragma unroll
+    for (int d = 0; d < SDC_DIM; ++d) a.Ubar[(i64)(1 + d) * Z + z] += keb * mom[d] * irho;
+    a.Ubar[(i64)(1 + SDC_DIM) * Z + z] += xb[SDC_NX - 1];
+#pragma unroll
+    for (int s = 0; s < SDC_NS; ++s) a.Ubar[(i64)(SDC_NH + s) * Z + z] += xb[s];
+  }
+  theta_block_sum(gl, gE, a.theta_part);
+}
+
+// thetabar[p] += sum over blocks of part[b][p], in block order (one block per p).
+extern "C" __global__ __launch_bounds__(256) void sdc_theta_reduce(ThetaReduceArgs a) {
+  __shared__ double sh[256];
+  const int p = blockIdx.x;
+  double t = 0.0;
+  for (i64 b = threadIdx.x; b < a.nblocks; b += blockDim.x) t += a.part[b * a.nparam + p];
+  sh[threadIdx.x] = t;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.thetabar[p] += sh[0];
+}
+
+extern "C" __global__ __launch_bounds__(256) void sdc_axpy(AxpyArgs a) {
+  const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < a.n) a.y[i] = fma(a.a, a.x[i], a.y[i]);
 }

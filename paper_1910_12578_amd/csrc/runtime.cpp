@@ -192,6 +192,8 @@ struct Prepared {
   sdcgen::Pattern pat;
   std::vector<double> lnA, b, E, Q, q;
   int64_t Z = 0;
+  std::vector<int64_t> box_off;  // [nbox + 1] zone offsets (batched boxes)
+  std::vector<int32_t> box_ext;  // [nbox][3]
   std::string source;
 };
 
@@ -206,17 +208,47 @@ int prepare(const sdc_config* cfg, const sdc_network* net, Prepared* P, std::str
     return SDC_ERR_ARG;
   }
   int64_t Z = 1;
+  const int64_t minn = c.advection ? 2 : 1;
   for (int d = 0; d < c.dim; ++d) {
-    const int64_t minn = c.advection ? 2 : 1;
-    if (c.n[d] < minn || c.n[d] > (int64_t(1) << 30)) {
-      *err = "zone counts must be in [2, 2^30] per direction (>= 1 without advection)";
-      return SDC_ERR_ARG;
-    }
     if (!(c.dx[d] > 0.0) || !std::isfinite(c.dx[d])) {
       *err = "dx must be positive and finite";
       return SDC_ERR_ARG;
     }
-    Z *= c.n[d];
+  }
+  if (c.nbox < 0) {
+    *err = "nbox must be >= 0";
+    return SDC_ERR_ARG;
+  }
+  if (c.nbox > 0) {
+    if (!c.box_n) {
+      *err = "box_n must not be NULL when nbox > 0";
+      return SDC_ERR_ARG;
+    }
+    P->box_off.assign(1, 0);
+    Z = 0;
+    for (int bx = 0; bx < c.nbox; ++bx) {
+      int64_t zb = 1;
+      for (int d = 0; d < 3; ++d) {
+        const int64_t e = d < c.dim ? c.box_n[3 * bx + d] : 1;
+        if (e < minn || e > (int64_t(1) << 20)) {
+          *err = "box extents must be in [2, 2^20] per direction (>= 1 without advection)";
+          return SDC_ERR_ARG;
+        }
+        P->box_ext.push_back((int32_t)e);
+        zb *= e;
+      }
+      Z += zb;
+      if (Z > (int64_t(1) << 31) - (int64_t)kBlock) break;
+      P->box_off.push_back(Z);
+    }
+  } else {
+    for (int d = 0; d < c.dim; ++d) {
+      if (c.n[d] < minn || c.n[d] > (int64_t(1) << 30)) {
+        *err = "zone counts must be in [2, 2^30] per direction (>= 1 without advection)";
+        return SDC_ERR_ARG;
+      }
+      Z *= c.n[d];
+    }
   }
   if (Z > (int64_t(1) << 31) - (int64_t)kBlock) {
     *err = "grid exceeds 2^31 zones";
@@ -328,10 +360,18 @@ struct sdc_handle_s {
   std::vector<double> tau;
   std::vector<std::vector<double>> S;
   hipModule_t mod = nullptr;
+  hipFunction_t f_advect_vjp = nullptr, f_trans_adj_first = nullptr, f_trans_adj = nullptr, f_source_vjp = nullptr,
+                f_theta_reduce = nullptr, f_axpy = nullptr;
+  // adjoint workspace (allocated on first use): forward replay nodes, stored
+  // node states of every iteration, adjoint arrays, parameter partials
+  std::vector<double*> adj_buf;
   hipFunction_t f_advect = nullptr, f_advect3d = nullptr, f_source = nullptr, f_solve = nullptr, f_first = nullptr,
                 f_node0 = nullptr, f_later = nullptr, f_fill = nullptr;
   void* d_params = nullptr;
   unsigned long long* d_stats = nullptr;
+  int64_t* d_box_off = nullptr;
+  int32_t* d_box_ext = nullptr;
+  int32_t* d_blk_box = nullptr;
   hipStream_t last_stream = nullptr;
   std::string err;
   // per-kernel timing
@@ -342,6 +382,11 @@ struct sdc_handle_s {
   };
   std::vector<Timed> timed;
   std::vector<hipEvent_t> event_pool;
+  // captured steps: one executable graph per buffer-rotation phase, valid for
+  // the (dt, work arrays) they were captured with
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t step_graph[2] = {nullptr, nullptr};
+  std::vector<uintptr_t> graph_key;
 };
 
 namespace {
@@ -368,7 +413,8 @@ int kind_of(const sdc_handle h, hipFunction_t f) {
   if (f == h->f_first) return SDC_K_TRANSITION_FIRST;
   if (f == h->f_node0) return SDC_K_TRANSITION_NODE0;
   if (f == h->f_later) return SDC_K_TRANSITION_LATER;
-  return SDC_K_FILL;
+  if (f == h->f_fill) return SDC_K_FILL;
+  return SDC_K_ADJOINT;
 }
 
 hipEvent_t take_event(sdc_handle h) {
@@ -429,6 +475,13 @@ int advect(sdc_handle h, const double* U, double* A, hipStream_t s) {
   a.gamma = c.gamma;
   a.alpha = c.alpha;
   a.slope = c.slope;
+  if (c.nbox > 0) {
+    a.nbox = c.nbox;
+    a.box_off = (const sdc_i64*)h->d_box_off;
+    a.box_ext = h->d_box_ext;
+    a.blk_box = h->d_blk_box;
+    return launch(h, h->f_advect, h->P.Z, &a, s);
+  }
   if (c.dim == 3 && h->f_advect3d) {
     // z-marching kernel: one 256-thread block per 64 x 4 column tile and z chunk
     const int spg = h->ns < 5 ? h->ns : 5, ngrp = (h->ns + spg - 1) / spg;
@@ -494,6 +547,197 @@ int sweep(sdc_handle h, double dt, int k, const sdc_nodes& n, hipStream_t s) {
   return SDC_OK;
 }
 
+void drop_graphs(sdc_handle h) {
+  for (auto& g : h->step_graph)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  h->graph_key.clear();
+}
+
+// Capture the K sweeps of one step with node 0 in n.U[0] into an executable
+// graph.  Capture runs on the handle's own stream: nothing executes.
+int capture_step(sdc_handle h, double dt, const sdc_nodes& n, hipGraphExec_t* out) {
+  if (!h->capture_stream) HIP_CHECK(h, hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
+  HIP_CHECK(h, hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
+  int rc = SDC_OK;
+  for (int k = 0; k < h->P.cfg.n_iters && rc == SDC_OK; ++k) rc = sweep(h, dt, k, n, h->capture_stream);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(h->capture_stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(h, SDC_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(h, SDC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  return SDC_OK;
+}
+
+// ---- adjoint
+struct AdjWork {
+  sdc_nodes F;                      // forward replay nodes
+  double* Ust[8][SDC_MAX_NODES];    // node states of iteration k+1 (m = 1..M)
+  double *Ub[SDC_MAX_NODES], *Ab[SDC_MAX_NODES], *Rb[SDC_MAX_NODES];  // [0] = node 0 adjoints
+  double *Abo[SDC_MAX_NODES], *Rbo[SDC_MAX_NODES];                    // previous iteration
+  double* part;                     // [nblocks][2 nreact]
+};
+
+int adjoint_workspace(sdc_handle h, AdjWork* W) {
+  const int M = h->M, K = h->P.cfg.n_iters;
+  const size_t zc = (size_t)h->nc * h->P.Z, zr = (size_t)h->nx * h->P.Z;
+  const size_t nblk = (h->P.Z + kBlock - 1) / kBlock;
+  std::vector<size_t> sizes;
+  // F: U, A (zc) and R (zr) per node, C (zc) per inner node
+  for (int j = 0; j <= M; ++j) {
+    sizes.push_back(zc);
+    sizes.push_back(zc);
+    sizes.push_back(zr);
+  }
+  for (int j = 0; j < M - 1; ++j) sizes.push_back(zc);
+  for (int k = 0; k < K; ++k)
+    for (int m = 1; m <= M; ++m) sizes.push_back(zc);
+  for (int j = 0; j <= M; ++j) {
+    sizes.push_back(zc);  // Ub
+    sizes.push_back(zc);  // Ab
+    sizes.push_back(zr);  // Rb
+    sizes.push_back(zc);  // Abo
+    sizes.push_back(zr);  // Rbo
+  }
+  sizes.push_back(nblk * 2 * (size_t)h->nra);
+  if (h->adj_buf.empty()) {
+    for (size_t n : sizes) {
+      double* p = nullptr;
+      if (hipMalloc((void**)&p, n * sizeof(double)) != hipSuccess) {
+        for (double* q : h->adj_buf) (void)hipFree(q);
+        h->adj_buf.clear();
+        return fail(h, SDC_ERR_NOMEM, "hipMalloc(adjoint workspace) failed");
+      }
+      h->adj_buf.push_back(p);
+    }
+  }
+  size_t i = 0;
+  std::memset(&W->F, 0, sizeof W->F);
+  for (int j = 0; j <= M; ++j) {
+    W->F.U[j] = h->adj_buf[i++];
+    W->F.A[j] = h->adj_buf[i++];
+    W->F.R[j] = h->adj_buf[i++];
+  }
+  for (int j = 0; j < M - 1; ++j) W->F.C[j] = h->adj_buf[i++];
+  for (int k = 0; k < K; ++k)
+    for (int m = 1; m <= M; ++m) W->Ust[k][m] = h->adj_buf[i++];
+  for (int j = 0; j <= M; ++j) {
+    W->Ub[j] = h->adj_buf[i++];
+    W->Ab[j] = h->adj_buf[i++];
+    W->Rb[j] = h->adj_buf[i++];
+    W->Abo[j] = h->adj_buf[i++];
+    W->Rbo[j] = h->adj_buf[i++];
+  }
+  W->part = h->adj_buf[i++];
+  return SDC_OK;
+}
+
+int advect_vjp(sdc_handle h, const double* U, const double* Abar, double* Ubar, hipStream_t s) {
+  const sdc_config& c = h->P.cfg;
+  AdvVjpArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.U = U;
+  a.Abar = Abar;
+  a.Ubar = Ubar;
+  a.Z = h->P.Z;
+  for (int d = 0; d < 3; ++d) {
+    a.n[d] = d < c.dim ? (int)c.n[d] : 1;
+    a.idx[d] = d < c.dim ? 1.0 / c.dx[d] : 0.0;
+  }
+  a.gamma = c.gamma;
+  a.alpha = c.alpha;
+  return launch(h, h->f_advect_vjp, h->P.Z, &a, s);
+}
+
+int theta_reduce(sdc_handle h, const double* part, double* thetabar, hipStream_t s) {
+  if (h->P.topo.nr == 0) return SDC_OK;
+  ThetaReduceArgs a{part, (h->P.Z + kBlock - 1) / kBlock, 2 * h->P.topo.nr, thetabar};
+  // one block per parameter
+  return launch(h, h->f_theta_reduce, (int64_t)a.nparam * kBlock, &a, s);
+}
+
+int step_adjoint(sdc_handle h, double dt, const double* Un, const double* Ubar1, double* Ubar0, double* thetabar,
+                 hipStream_t s) {
+  const int M = h->M, K = h->P.cfg.n_iters;
+  const int64_t zc = (int64_t)h->nc * h->P.Z, zr = (int64_t)h->nx * h->P.Z;
+  AdjWork W;
+  int rc = adjoint_workspace(h, &W);
+  if (rc) return rc;
+  // forward replay from U^n, keeping every iteration's node states
+  HIP_CHECK(h, hipMemcpyAsync(W.F.U[0], Un, zc * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if ((rc = advect(h, W.F.U[0], W.F.A[0], s))) return rc;
+  if ((rc = source(h, W.F.U[0], W.F.R[0], s))) return rc;
+  if (!h->P.cfg.advection)
+    for (int j = 1; j <= M; ++j)
+      if ((rc = fill(h, W.F.A[j], zc, 0.0, s))) return rc;
+  for (int k = 0; k < K; ++k) {
+    if ((rc = sweep(h, dt, k, W.F, s))) return rc;
+    for (int m = 1; m <= M; ++m)
+      HIP_CHECK(h, hipMemcpyAsync(W.Ust[k][m], W.F.U[m], zc * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  // reverse
+  for (int j = 0; j <= M; ++j) {
+    if ((rc = fill(h, W.Ub[j], zc, 0.0, s)) || (rc = fill(h, W.Ab[j], zc, 0.0, s)) ||
+        (rc = fill(h, W.Rb[j], zr, 0.0, s)))
+      return rc;
+  }
+  HIP_CHECK(h, hipMemcpyAsync(W.Ub[M], Ubar1, zc * sizeof(double), hipMemcpyDeviceToDevice, s));
+  const bool adv = h->P.cfg.advection != 0;
+  for (int k = K - 1; k >= 0; --k) {
+    for (int j = 1; j <= M; ++j)
+      if ((rc = fill(h, W.Abo[j], zc, 0.0, s)) || (rc = fill(h, W.Rbo[j], zr, 0.0, s))) return rc;
+    if (adv && (rc = advect_vjp(h, W.Ust[k][M], W.Ab[M], W.Ub[M], s))) return rc;
+    for (int m = M - 1; m >= 0; --m) {
+      TransAdjArgs a;
+      std::memset(&a, 0, sizeof a);
+      a.Z = h->P.Z;
+      a.m = m;
+      a.M = M;
+      a.first = k == 0;
+      a.dt = dt;
+      a.dtm = (h->tau[m + 1] - h->tau[m]) * dt;
+      for (int i = 0; i < M; ++i)
+        for (int j = 0; j <= M; ++j) a.S[i][j] = h->S[i][j];
+      a.Uout = W.Ust[k][m + 1];
+      a.Uoutbar = W.Ub[m + 1];
+      a.Routbar = W.Rb[m + 1];
+      a.Umbar = W.Ub[m];
+      a.Ambar = (k == 0 || m >= 1) ? W.Ab[m] : nullptr;
+      for (int j = 0; j <= M; ++j) {
+        a.Aoldbar[j] = j == 0 ? W.Ab[0] : W.Abo[j];
+        a.Roldbar[j] = j == 0 ? W.Rb[0] : W.Rbo[j];
+      }
+      a.P = h->d_params;
+      a.gm1 = h->P.cfg.gamma - 1.0;
+      a.tau = h->P.cfg.pivot_threshold;
+      a.theta_part = W.part;
+      if ((rc = launch(h, k == 0 ? h->f_trans_adj_first : h->f_trans_adj, h->P.Z, &a, s))) return rc;
+      if ((rc = theta_reduce(h, W.part, thetabar, s))) return rc;
+      if (m >= 1 && adv && (rc = advect_vjp(h, W.Ust[k][m], W.Ab[m], W.Ub[m], s))) return rc;
+    }
+    // iteration k's node adjoints: the "old" accumulators; its states feed
+    // only Newton guesses, so their adjoints restart from zero
+    for (int j = 1; j <= M; ++j) {
+      std::swap(W.Ab[j], W.Abo[j]);
+      std::swap(W.Rb[j], W.Rbo[j]);
+      if ((rc = fill(h, W.Ub[j], zc, 0.0, s))) return rc;
+    }
+  }
+  // node 0: U^n itself, A^0 = A(U^n), R^0 = R(U^n)
+  HIP_CHECK(h, hipMemcpyAsync(Ubar0, W.Ub[0], zc * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (adv && (rc = advect_vjp(h, Un, W.Ab[0], Ubar0, s))) return rc;
+  SourceVjpArgs sv{h->P.Z, Un, W.Rb[0], Ubar0, h->d_params, h->P.cfg.gamma - 1.0, W.part};
+  if ((rc = launch(h, h->f_source_vjp, h->P.Z, &sv, s))) return rc;
+  return theta_reduce(h, W.part, thetabar, s);
+}
+
 int check_handle(sdc_handle h) {
   if (!h) return fail(nullptr, SDC_ERR_ARG, "null handle");
   return SDC_OK;
@@ -520,6 +764,9 @@ int sdc_config_default(sdc_config* cfg) {
   cfg->newton_tol = 1e-13;
   cfg->newton_maxiter = 50;
   cfg->pivot_threshold = 0.1;
+  cfg->nbox = 0;
+  cfg->box_n = nullptr;
+  cfg->graph = 0;
   return SDC_OK;
 }
 
@@ -587,7 +834,10 @@ int sdc_init(const sdc_config* cfg, const sdc_network* net, sdc_handle* out) {
   } fns[] = {{&h->f_advect, "sdc_advect"},         {&h->f_source, "sdc_source"},
              {&h->f_solve, "sdc_reaction_solve"},  {&h->f_first, "sdc_transition_first"},
              {&h->f_node0, "sdc_transition_node0"}, {&h->f_later, "sdc_transition_later"},
-             {&h->f_fill, "sdc_fill"}};
+             {&h->f_fill, "sdc_fill"}, {&h->f_advect_vjp, "sdc_advect_vjp"},
+             {&h->f_trans_adj_first, "sdc_transition_adjoint_first"}, {&h->f_trans_adj, "sdc_transition_adjoint"},
+             {&h->f_source_vjp, "sdc_source_vjp"}, {&h->f_theta_reduce, "sdc_theta_reduce"},
+             {&h->f_axpy, "sdc_axpy"}};
   for (auto& fn : fns) {
     e = hipModuleGetFunction(fn.f, h->mod, fn.name);
     if (e != hipSuccess) return bail(SDC_ERR_HIP, std::string("missing kernel ") + fn.name);
@@ -595,7 +845,7 @@ int sdc_init(const sdc_config* cfg, const sdc_network* net, sdc_handle* out) {
   // SDC_ADVECT3D=1 selects the z-marching 3D kernel (needs 32-bit offsets
   // inside one component array); the zone-per-thread kernel is the default
   const char* ev = std::getenv("SDC_ADVECT3D");
-  if (h->P.cfg.dim == 3 && h->P.Z < (int64_t(1) << 28) && ev && ev[0] == '1') {
+  if (h->P.cfg.dim == 3 && h->P.cfg.nbox == 0 && h->P.Z < (int64_t(1) << 28) && ev && ev[0] == '1') {
     e = hipModuleGetFunction(&h->f_advect3d, h->mod, "sdc_advect3d");
     if (e != hipSuccess) return bail(SDC_ERR_HIP, "missing kernel sdc_advect3d");
   }
@@ -604,6 +854,24 @@ int sdc_init(const sdc_config* cfg, const sdc_network* net, sdc_handle* out) {
   if (e != hipSuccess) return bail(SDC_ERR_NOMEM, "hipMalloc(params) failed");
   e = hipMemcpy(h->d_params, img.data(), img.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e != hipSuccess) return bail(SDC_ERR_HIP, std::string("hipMemcpy(params): ") + hipGetErrorString(e));
+  if (h->P.cfg.nbox > 0) {
+    const int nbox = h->P.cfg.nbox;
+    const int64_t nblk = (h->P.Z + kBlock - 1) / kBlock;
+    std::vector<int32_t> blk(nblk);
+    int bx = 0;
+    for (int64_t q = 0; q < nblk; ++q) {
+      while (q * kBlock >= h->P.box_off[bx + 1]) ++bx;
+      blk[q] = bx;
+    }
+    if (hipMalloc((void**)&h->d_box_off, (nbox + 1) * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc((void**)&h->d_box_ext, 3 * nbox * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc((void**)&h->d_blk_box, nblk * sizeof(int32_t)) != hipSuccess)
+      return bail(SDC_ERR_NOMEM, "hipMalloc(box tables) failed");
+    if (hipMemcpy(h->d_box_off, h->P.box_off.data(), (nbox + 1) * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->d_box_ext, h->P.box_ext.data(), 3 * nbox * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->d_blk_box, blk.data(), nblk * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(SDC_ERR_HIP, "hipMemcpy(box tables) failed");
+  }
   e = hipMalloc((void**)&h->d_stats, SDC_NSTATS * sizeof(unsigned long long));
   if (e != hipSuccess) return bail(SDC_ERR_NOMEM, "hipMalloc(stats) failed");
   e = hipMemset(h->d_stats, 0, SDC_NSTATS * sizeof(unsigned long long));
@@ -623,7 +891,13 @@ int sdc_destroy(sdc_handle h) {
     (void)hipEventDestroy(t.b);
   }
   for (auto e : h->event_pool) (void)hipEventDestroy(e);
+  drop_graphs(h);
+  if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+  for (double* p : h->adj_buf) (void)hipFree(p);
   if (h->d_params) (void)hipFree(h->d_params);
+  if (h->d_box_off) (void)hipFree(h->d_box_off);
+  if (h->d_box_ext) (void)hipFree(h->d_box_ext);
+  if (h->d_blk_box) (void)hipFree(h->d_blk_box);
   if (h->d_stats) (void)hipFree(h->d_stats);
   if (h->mod) (void)hipModuleUnload(h->mod);
   delete h;
@@ -707,9 +981,37 @@ int sdc_step(sdc_handle h, double dt, int32_t nsteps, double* U, const sdc_nodes
   if (!h->P.cfg.advection)
     for (int j = 1; j <= h->M; ++j)
       if ((rc = fill(h, n.A[j], (int64_t)h->nc * h->P.Z, 0.0, s))) return rc;
+  const bool use_graph = h->P.cfg.graph && !h->profile;
+  if (use_graph) {
+    // key: dt and every work pointer; a change re-captures both phases
+    std::vector<uintptr_t> key;
+    uint64_t dtbits;
+    std::memcpy(&dtbits, &dt, sizeof dt);
+    key.push_back((uintptr_t)dtbits);
+    for (int j = 0; j < SDC_MAX_NODES; ++j) {
+      key.push_back((uintptr_t)n.U[j]);
+      key.push_back((uintptr_t)n.A[j]);
+      key.push_back((uintptr_t)n.R[j]);
+    }
+    for (int j = 0; j < SDC_MAX_NODES - 2; ++j) key.push_back((uintptr_t)n.C[j]);
+    if (key != h->graph_key) {
+      drop_graphs(h);
+      sdc_nodes swapped = n;
+      std::swap(swapped.U[0], swapped.U[h->M]);
+      std::swap(swapped.A[0], swapped.A[h->M]);
+      std::swap(swapped.R[0], swapped.R[h->M]);
+      if ((rc = capture_step(h, dt, n, &h->step_graph[0]))) return rc;
+      if ((rc = capture_step(h, dt, swapped, &h->step_graph[1]))) return rc;
+      h->graph_key = key;
+    }
+  }
   for (int step = 0; step < nsteps; ++step) {
-    for (int k = 0; k < h->P.cfg.n_iters; ++k)
-      if ((rc = sweep(h, dt, k, n, s))) return rc;
+    if (use_graph) {
+      HIP_CHECK(h, hipGraphLaunch(h->step_graph[step & 1], s));
+    } else {
+      for (int k = 0; k < h->P.cfg.n_iters; ++k)
+        if ((rc = sweep(h, dt, k, n, s))) return rc;
+    }
     // the last node becomes node 0 of the next step
     std::swap(n.U[0], n.U[h->M]);
     std::swap(n.A[0], n.A[h->M]);
@@ -717,6 +1019,24 @@ int sdc_step(sdc_handle h, double dt, int32_t nsteps, double* U, const sdc_nodes
   }
   HIP_CHECK(h, hipMemcpyAsync(U, n.U[0], bytesU, hipMemcpyDeviceToDevice, s));
   return SDC_OK;
+}
+
+int sdc_step_adjoint(sdc_handle h, double dt, const double* U_n, const double* Ubar_np1, double* Ubar_n,
+                     double* thetabar, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!U_n || !Ubar_np1 || !Ubar_n || (!thetabar && h->P.topo.nr > 0))
+    return fail(h, SDC_ERR_ARG, "null array");
+  if (!std::isfinite(dt) || dt <= 0.0) return fail(h, SDC_ERR_ARG, "dt must be positive");
+  if ((const double*)Ubar_n == Ubar_np1 || (const double*)Ubar_n == U_n)
+    return fail(h, SDC_ERR_ARG, "Ubar_n must not alias U_n or Ubar_np1");
+  const sdc_config& c = h->P.cfg;
+  if (c.nbox > 0) return fail(h, SDC_ERR_UNSUPPORTED, "the adjoint supports single grids only");
+  if (c.advection && !(c.slope == 0 && c.alpha > 0.0))
+    return fail(h, SDC_ERR_UNSUPPORTED, "the adjoint needs the smooth mode: slope 0 and a frozen alpha > 0");
+  if (c.n_iters > 8) return fail(h, SDC_ERR_UNSUPPORTED, "the adjoint supports up to 8 SDC iterations");
+  hipStream_t s = (hipStream_t)stream;
+  h->last_stream = s;
+  return step_adjoint(h, dt, U_n, Ubar_np1, Ubar_n, thetabar, s);
 }
 
 int sdc_stats(sdc_handle h, int64_t* out) {

@@ -209,3 +209,43 @@ def test_bad_arguments_raise():
         h.advective_term(U[:, :10].contiguous())
     with pytest.raises(TypeError):
         h.advective_term(U.float())
+
+
+@pytest.mark.parametrize("name", ["chain1d", "net2d"])
+def test_graph_replay_matches_eager_bitwise(name):
+    """Captured steps replayed several times, with eager work in between,
+    equal plain launches bit for bit after every call."""
+    import torch
+    w, prob, hg = make(name, graph=1)
+    _, _, he = make(name, graph=0)
+    nc = w["U0"].shape[0]
+    a = to_gpu(w["U0"].reshape(nc, -1))
+    b = a.clone()
+    wa, wb = hg.alloc_nodes(), he.alloc_nodes()
+    for rep in range(4):
+        hg.step(w["dt"], 2 + rep % 2, a, wa)
+        scratch = torch.randn(1000, device="cuda").abs().sum()  # unrelated eager work
+        he.step(w["dt"], 2 + rep % 2, b, wb)
+        torch.cuda.synchronize()
+        assert bool((a == b).all()), f"replay {rep} differs"
+        assert bool(torch.isfinite(scratch))
+    sa, sb = hg.stats(), he.stats()
+    assert sa == sb
+
+
+def test_graph_step_latency_report():
+    """Per-step wall time of the 64-zone chain with and without graphs (report)."""
+    import time
+    import torch
+    w, prob, hg = make("chain1d", graph=1)
+    _, _, he = make("chain1d", graph=0)
+    nc = w["U0"].shape[0]
+    for h, label in ((he, "launches"), (hg, "graph")):
+        U = to_gpu(w["U0"].reshape(nc, -1))
+        work = h.alloc_nodes()
+        h.step(w["dt"], 10, U, work)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.step(w["dt"], 200, U, work)
+        torch.cuda.synchronize()
+        print(f"chain1d {label}: {1e6 * (time.perf_counter() - t0) / 200:.1f} us per step")
