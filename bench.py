@@ -101,6 +101,80 @@ def run_gpu(w, precision, steps, warmup):
     return res
 
 
+def run_adjoint_ratio(nsteps=20):
+    """Forward vs backward time of the adjoint workload (256^2, 7 species,
+    smooth mode): forward = nsteps SDC steps keeping one checkpoint per step;
+    backward = nsteps step adjoints (replay + reverse sweeps)."""
+    import torch
+    from paper_1910_12578_amd import SDC, config_from_workload
+    w = si.workload("adjoint2d")
+    h = SDC(config_from_workload(w), w["network"])
+    nc = w["U0"].shape[0]
+    U0 = torch.from_numpy(w["U0"].reshape(nc, -1)).to("cuda")
+    work = h.alloc_nodes()
+    dt = w["dt"]
+    seed = torch.zeros_like(U0)
+    seed[2 + w["dim"]:2 + w["dim"] + w["network"]["nspec"]] = -torch.tensor(
+        w["network"]["q"], device="cuda")[:, None] * float(np.prod(w["dx"]))
+    thetabar = torch.zeros(2 * h.nreact, dtype=torch.float64, device="cuda")
+
+    def forward():
+        U = U0.clone()
+        ck = []
+        for _ in range(nsteps):
+            ck.append(U.clone())
+            h.step(dt, 1, U, work)
+        return U, ck
+
+    def backward(ck):
+        Ub = seed.clone()
+        for U_n in reversed(ck):
+            Ub, _ = h.step_adjoint(dt, U_n, Ub, None, thetabar)
+        return Ub
+
+    _, ck = forward()
+    backward(ck)  # warm (allocates the adjoint workspace)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, ck = forward()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    backward(ck)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    h.close()
+    return dict(workload=f"adjoint2d 256x256, 7 species / 10 reactions, smooth mode, {nsteps} steps",
+                forward_ms=1e3 * (t1 - t0), backward_ms=1e3 * (t2 - t1), ratio=(t2 - t1) / (t1 - t0))
+
+
+def run_boxes(steps, warmup, precision):
+    """Batched boxes: 4096 periodic boxes, edges in {8,16,32,64}, one launch per kernel."""
+    import torch
+    from paper_1910_12578_amd import SDC, config_from_workload
+    w = si.boxes_workload()
+    h = SDC(config_from_workload(w, precision=precision), w["network"])
+    nc = w["U0"].shape[0]
+    U = torch.from_numpy(w["U0"]).to("cuda")
+    work = h.alloc_nodes()
+    h.step(w["dt"], warmup, U, work)
+    torch.cuda.synchronize()
+    h.stats_reset()
+    t0 = time.perf_counter()
+    h.step(w["dt"], steps, U, work)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = h.stats()
+    Z = w["U0"].shape[1]
+    out = dict(workload=f"{len(w['box_n'])} boxes, edges in {{8,16,32,64}}, {Z} zones, 0.2 CFL step",
+               zone_updates=Z * steps / el, ms_per_step=1e3 * el / steps,
+               mean_newton=st["iters"] / max(st["solves"] - st["failed"], 1), failed=st["failed"],
+               newton_hist={i: v for i, v in enumerate(st["hist"]) if v})
+    h.close()
+    del U, work
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, edge):
     """The oracle on an edge^3 corner of the same initial state, one step."""
     from threadpoolctl import threadpool_limits
@@ -130,6 +204,8 @@ def main():
     ap.add_argument("--precision", default="both", choices=("fp64", "mixed", "both"))
     ap.add_argument("--cpu-edge", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward time ratio")
+    ap.add_argument("--boxes", action="store_true", help="also time the 4096-box batched workload")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (calibrates HBM byte counters)")
     a = ap.parse_args()
@@ -151,7 +227,7 @@ def main():
     tr = head["transition"]
     achieved = tr["flops"] / tr["seconds"] / 1e12 if tr["seconds"] > 0 else 0.0
     out = dict(
-        metric="SDC zone-updates/s, 256^3 x 13 species (FP64; mixed beside it)",
+        metric="SDC zone-updates/s, 256^3 x 13 species, FP64 (mixed and adjoint/forward time beside it)",
         value=head["zone_updates"],
         unit="zone-updates/s",
         n_gpus=1, steps=a.steps, warmup=a.warmup,
@@ -176,6 +252,12 @@ def main():
                             speedup_vs_fp64=runs["mixed"]["zone_updates"] / runs["fp64"]["zone_updates"],
                             mean_newton_iterations=runs["mixed"]["mean_newton"],
                             kernels_ms=runs["mixed"]["profile"])
+    if not a.no_adjoint:
+        print("[bench] adjoint/forward ratio", file=sys.stderr, flush=True)
+        out["adjoint"] = run_adjoint_ratio()
+    if a.boxes:
+        print("[bench] batched boxes", file=sys.stderr, flush=True)
+        out["boxes"] = {name: run_boxes(a.steps, a.warmup, prec) for name, prec in (("fp64", 0), ("mixed", 1))}
     if a.copy_probe_mib:
         import torch
         n = a.copy_probe_mib * (1 << 20) // 8
