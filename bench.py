@@ -59,7 +59,19 @@ def transition_model(h, work_kinds, stats, nlaunch):
     return flops, bytes_, per_iter, per_solve
 
 
-def run_gpu(w, precision, steps, warmup):
+def set_schedule(h, schedule, dt, U, work):
+    """'auto': time every Newton schedule on the initial state (untimed
+    set-up, like a GEMM heuristic); 'O,C': fixed occupancy variant and cap."""
+    t0 = time.perf_counter()
+    if schedule == "auto":
+        occ2, cap = h.autotune(dt, U, work)
+    else:
+        occ2, cap = (int(v) for v in schedule.split(","))
+        h.set_schedule(occ2, cap)
+    return dict(occ2=occ2, cap=cap, mode=schedule, setup_s=round(time.perf_counter() - t0, 3))
+
+
+def run_gpu(w, precision, steps, warmup, schedule="auto"):
     import torch
     from paper_1910_12578_amd import SDC, config_from_workload
     cfg = config_from_workload(w, precision=precision)
@@ -69,6 +81,7 @@ def run_gpu(w, precision, steps, warmup):
     work = h.alloc_nodes()
     dt = w["dt"]
     stream = torch.cuda.current_stream()
+    sched = set_schedule(h, schedule, dt, U, work)
     h.step(dt, warmup, U, work)
     torch.cuda.synchronize()
     h.stats_reset()
@@ -84,7 +97,9 @@ def run_gpu(w, precision, steps, warmup):
     ok = bool(torch.isfinite(U).all().item())
     kinds = ("transition_first", "transition_node0", "transition_later")
     nlaunch = {k: prof[k][1] for k in kinds}
-    t_trans = sum(prof[k][0] for k in kinds) * 1e-3
+    # one transition = its fast-pass kernel plus the finish kernel of the
+    # zones it deferred; both carry the Newton work the flop model counts
+    t_trans = (sum(prof[k][0] for k in kinds) + prof["finish"][0]) * 1e-3
     flops, bytes_, per_iter, per_solve = transition_model(h, kinds, st, nlaunch)
     res = dict(
         elapsed=elapsed, ms_per_step=1e3 * elapsed / steps, zone_updates=w["U0"][0].size * steps / elapsed,
@@ -93,7 +108,7 @@ def run_gpu(w, precision, steps, warmup):
         transition=dict(seconds=t_trans, flops=flops, bytes=bytes_, flops_per_iter=per_iter,
                         flops_per_solve=per_solve,
                         avg_launch_ms=1e3 * t_trans / max(sum(nlaunch.values()), 1)),
-        cost_model=h.cost_model(),
+        cost_model=h.cost_model(), schedule=sched,
     )
     h.close()
     del U, work
@@ -147,7 +162,7 @@ def run_adjoint_ratio(nsteps=20):
                 forward_ms=1e3 * (t1 - t0), backward_ms=1e3 * (t2 - t1), ratio=(t2 - t1) / (t1 - t0))
 
 
-def run_boxes(steps, warmup, precision):
+def run_boxes(steps, warmup, precision, schedule="auto"):
     """Batched boxes: 4096 periodic boxes, edges in {8,16,32,64}, one launch per kernel."""
     import torch
     from paper_1910_12578_amd import SDC, config_from_workload
@@ -156,6 +171,7 @@ def run_boxes(steps, warmup, precision):
     nc = w["U0"].shape[0]
     U = torch.from_numpy(w["U0"]).to("cuda")
     work = h.alloc_nodes()
+    sched = set_schedule(h, schedule, w["dt"], U, work)
     h.step(w["dt"], warmup, U, work)
     torch.cuda.synchronize()
     h.stats_reset()
@@ -168,7 +184,7 @@ def run_boxes(steps, warmup, precision):
     out = dict(workload=f"{len(w['box_n'])} boxes, edges in {{8,16,32,64}}, {Z} zones, 0.2 CFL step",
                zone_updates=Z * steps / el, ms_per_step=1e3 * el / steps,
                mean_newton=st["iters"] / max(st["solves"] - st["failed"], 1), failed=st["failed"],
-               newton_hist={i: v for i, v in enumerate(st["hist"]) if v})
+               newton_hist={i: v for i, v in enumerate(st["hist"]) if v}, schedule=sched)
     h.close()
     del U, work
     torch.cuda.empty_cache()
@@ -206,6 +222,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward time ratio")
     ap.add_argument("--boxes", action="store_true", help="also time the 4096-box batched workload")
+    ap.add_argument("--schedule", default="auto",
+                    help="Newton kernel schedule: 'auto' (autotune before warmup) or 'OCC2,CAP', e.g. 0,0")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (calibrates HBM byte counters)")
     a = ap.parse_args()
@@ -221,7 +239,7 @@ def main():
     for name, prec in (("fp64", 0), ("mixed", 1)):
         if a.precision in (name, "both"):
             print(f"[bench] {name}: warmup {a.warmup}, timed {a.steps} steps", file=sys.stderr, flush=True)
-            runs[name] = run_gpu(w, prec, a.steps, a.warmup)
+            runs[name] = run_gpu(w, prec, a.steps, a.warmup, a.schedule)
             print(f"[bench] {name}: {runs[name]['zone_updates']:.4e} zone-updates/s", file=sys.stderr, flush=True)
     head = runs.get("fp64") or runs["mixed"]
     tr = head["transition"]
@@ -238,11 +256,13 @@ def main():
         config=dict(workload=f"{a.workload} {'x'.join(map(str, w['shape']))}, {w['network']['nspec']} species / "
                              f"{w['network']['nreact']} reactions, {w['n_nodes']} Gauss-Lobatto nodes, "
                              f"K={w['n_iters']}", zones=Z, dt=w["dt"]),
-        roofline=dict(bound="alu", kernel="sdc_transition_* (fused quadrature + explicit update + Newton)",
+        roofline=dict(bound="alu", kernel="sdc_transition_* + sdc_transition_finish "
+                                          "(fused quadrature + explicit update + Newton)",
                       achieved=achieved, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
                       frac=achieved / PEAK_FP64_TFLOPS, traffic=None,
                       hbm_achieved_GBs=tr["bytes"] / tr["seconds"] / 1e9 if tr["seconds"] > 0 else 0.0,
                       avg_launch_ms=tr["avg_launch_ms"]),
+        schedule=head["schedule"],
         mean_newton_iterations=head["mean_newton"],
         newton_failed=head["stats"]["failed"],
         kernels_ms=head["profile"],
@@ -250,14 +270,15 @@ def main():
     if "mixed" in runs and "fp64" in runs:
         out["mixed"] = dict(value=runs["mixed"]["zone_updates"], ms_per_step=runs["mixed"]["ms_per_step"],
                             speedup_vs_fp64=runs["mixed"]["zone_updates"] / runs["fp64"]["zone_updates"],
-                            mean_newton_iterations=runs["mixed"]["mean_newton"],
+                            mean_newton_iterations=runs["mixed"]["mean_newton"], schedule=runs["mixed"]["schedule"],
                             kernels_ms=runs["mixed"]["profile"])
     if not a.no_adjoint:
         print("[bench] adjoint/forward ratio", file=sys.stderr, flush=True)
         out["adjoint"] = run_adjoint_ratio()
     if a.boxes:
         print("[bench] batched boxes", file=sys.stderr, flush=True)
-        out["boxes"] = {name: run_boxes(a.steps, a.warmup, prec) for name, prec in (("fp64", 0), ("mixed", 1))}
+        out["boxes"] = {name: run_boxes(a.steps, a.warmup, prec, a.schedule)
+                        for name, prec in (("fp64", 0), ("mixed", 1))}
     if a.copy_probe_mib:
         import torch
         n = a.copy_probe_mib * (1 << 20) // 8

@@ -113,6 +113,9 @@ typedef struct {
   /* 1: sdc_step replays one captured HIP graph per step (per buffer-rotation
    * phase); 0 (default): plain launches.  Profiling forces launches. */
   int32_t graph;
+  /* 1: the first sdc_step call runs sdc_autotune on its input; 0 (default):
+   * use the schedule set with sdc_set_schedule or the cached tuning. */
+  int32_t autotune;
 } sdc_config;
 
 /*
@@ -220,6 +223,25 @@ int sdc_set_params(sdc_handle h, const double* lnA, const double* E);
 int sdc_step_adjoint(sdc_handle h, double dt, const double* U_n, const double* Ubar_np1, double* Ubar_n,
                      double* thetabar, void* stream);
 
+/*
+ * Kernel schedule of the Newton kernels: occ2 = 1 selects the variants built
+ * for two wavefronts per SIMD (smaller register budget), occ2 = 0 the
+ * compiler's budget; cap > 0 stops the fast Newton pass after `cap`
+ * iterations and finishes the zones still unconverged in a second kernel,
+ * which packs the slow tail of the Newton counts into dense wavefronts
+ * (cap = 0: no cap).  Every schedule produces bitwise-identical results.
+ */
+int sdc_set_schedule(sdc_handle h, int32_t occ2, int32_t cap);
+int sdc_get_schedule(sdc_handle h, int32_t* occ2, int32_t* cap);
+
+/*
+ * Time every schedule (occ2 in {0,1} x cap in {0,4,5,6}) on one SDC step from
+ * U (read only; `work` is scratch) with HIP events on `stream`, keep the
+ * fastest, and cache the choice on disk per kernel source and zone count.
+ * Newton statistics are left unchanged.  Synchronises.
+ */
+int sdc_autotune(sdc_handle h, double dt, const double* U, const sdc_nodes* work, void* stream);
+
 /* Kernel kinds for sdc_profile_read. */
 #define SDC_K_ADVECT 0
 #define SDC_K_SOURCE 1
@@ -229,7 +251,8 @@ int sdc_step_adjoint(sdc_handle h, double dt, const double* U_n, const double* U
 #define SDC_K_TRANSITION_LATER 5
 #define SDC_K_FILL 6
 #define SDC_K_ADJOINT 7  /* every kernel of the adjoint pass */
-#define SDC_NKINDS 8
+#define SDC_K_FINISH 8   /* second-stage kernels of capped or guarded Newton solves */
+#define SDC_NKINDS 9
 
 /*
  * Per-kernel timing: while enabled, every launch is bracketed by HIP events

@@ -24,9 +24,9 @@ EXPORTS = ("sdc_config_default", "sdc_init", "sdc_destroy", "sdc_last_error", "s
            "sdc_advective_term", "sdc_source", "sdc_reaction_solve", "sdc_sweep", "sdc_step",
            "sdc_stats", "sdc_stats_reset", "sdc_set_params", "sdc_compile_only",
            "sdc_generated_source", "sdc_profile_enable", "sdc_profile_read", "sdc_cost_model",
-           "sdc_step_adjoint")
+           "sdc_step_adjoint", "sdc_set_schedule", "sdc_get_schedule", "sdc_autotune")
 KINDS = ("advect", "source", "solve", "transition_first", "transition_node0", "transition_later", "fill",
-         "adjoint")
+         "adjoint", "finish")
 
 
 class SDCError(RuntimeError):
@@ -47,7 +47,7 @@ class Config(ctypes.Structure):
                 ("advection", c_int32), ("slope", c_int32), ("alpha", c_double),
                 ("newton_tol", c_double), ("newton_maxiter", c_int32),
                 ("pivot_threshold", c_double), ("nbox", c_int32), ("box_n", POINTER(c_int64)),
-                ("graph", c_int32)]
+                ("graph", c_int32), ("autotune", c_int32)]
 
 
 class Nodes(ctypes.Structure):
@@ -90,6 +90,9 @@ def lib():
         L.sdc_profile_read.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int64)]
         L.sdc_cost_model.argtypes = [c_void_p, POINTER(c_int64)]
         L.sdc_step_adjoint.argtypes = [c_void_p, c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+        L.sdc_set_schedule.argtypes = [c_void_p, c_int32, c_int32]
+        L.sdc_get_schedule.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_int32)]
+        L.sdc_autotune.argtypes = [c_void_p, c_double, c_void_p, POINTER(Nodes), c_void_p]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype or c_int
         _lib = L
@@ -132,7 +135,7 @@ def make_config(cfg):
     for key in ("gamma", "alpha", "newton_tol", "pivot_threshold"):
         if key in cfg:
             setattr(c, key, float(cfg[key]))
-    for key in ("n_nodes", "n_iters", "precision", "advection", "slope", "newton_maxiter", "graph"):
+    for key in ("n_nodes", "n_iters", "precision", "advection", "slope", "newton_maxiter", "graph", "autotune"):
         if key in cfg:
             setattr(c, key, int(cfg[key]))
     return c
@@ -294,6 +297,21 @@ class SDC:
                                       self._ptr(Ubar_n, self.ncomp), c_void_p(thetabar.data_ptr()),
                                       self._stream(stream)), self._h)
         return Ubar_n, thetabar
+
+    def set_schedule(self, occ2, cap):
+        _check(lib().sdc_set_schedule(self._h, int(occ2), int(cap)), self._h)
+
+    def schedule(self):
+        o, c = c_int32(), c_int32()
+        _check(lib().sdc_get_schedule(self._h, byref(o), byref(c)), self._h)
+        return o.value, c.value
+
+    def autotune(self, dt, U, work=None, stream=None):
+        work = self.alloc_nodes() if work is None else work
+        n = self._nodes(work)
+        _check(lib().sdc_autotune(self._h, float(dt), self._ptr(U, self.ncomp), byref(n), self._stream(stream)),
+               self._h)
+        return self.schedule()
 
     def stats(self):
         out = (c_int64 * NSTATS)()

@@ -10,7 +10,20 @@ typedef struct {
   double tol;   // Newton stopping tolerance
   double tau;   // pivot threshold of the fixed-order LU
   int maxiter;
+  int cap;      // iterations of the fast pass before a zone is deferred (>= maxiter: never)
 } NewtonCtl;
+
+// Zones deferred by the fast Newton pass (iteration cap reached, or a pivot
+// below tau times its column maximum) and finished by a separate kernel.
+typedef struct {
+  sdc_i64* z;         // [capacity] zone index
+  int* it;            // [capacity] iterations done; -i: the pivot guard stopped iteration i
+  double* x;          // [NX][capacity] current iterate
+  double* b;          // [NX][capacity] right-hand side
+  double* aux;        // [2 + DIM][capacity] rho, kinetic energy, momenta (transitions)
+  unsigned* count;    // entries written
+  sdc_i64 capacity;
+} DeferQueue;
 
 typedef struct {
   const double* U;
@@ -41,6 +54,7 @@ typedef struct {
   double gm1;
   NewtonCtl ctl;
   unsigned long long* stats;
+  DeferQueue q;
 } SolveArgs;
 
 typedef struct {
@@ -70,6 +84,7 @@ typedef struct {
   double gm1;
   NewtonCtl ctl;
   unsigned long long* stats;
+  DeferQueue q;
 } TransArgs;
 
 typedef struct {

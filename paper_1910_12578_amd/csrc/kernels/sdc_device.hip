@@ -516,22 +516,26 @@ __device__ __attribute__((noinline)) DenseResult dense_newton(VecX xv, VecX bv, 
   return out;
 }
 
-// Solve x - dt_m R(x; rho) = b by Newton from the guess in x.  Stops when
-// max_i |delta_i| / s_i <= tol (s = rho for species, |b_e| for energy), after
-// at least one iteration; returns the iteration count or -1.  MT is the type
-// of the Newton matrix and its LU factors (double, or float for the mixed
-// mode where the residual and the update stay in double).
+// Fast Newton pass for x - dt_m R(x; rho) = b from the iterate in x, running
+// iterations it0..itmax.  Stops when max_i |delta_i| / s_i <= tol (s = rho for
+// species, |b_e| for energy).  Returns the last iteration index and a status:
+// 0 converged, 1 no convergence by itmax, 2 the pivot guard stopped iteration
+// `it` before it changed x, 3 non-finite step.  MT is the type of the Newton
+// matrix and its LU factors (double, or float in the mixed mode where the
+// residual and the update stay in double).  No calls: everything in registers.
 template <class MT>
-__device__ __forceinline__ int newton_solve(double* x, const double* b, double rho, double dtm, ParamPtr P,
-                                            double gm1, const NewtonCtl& ctl, int& fallbacks) {
-  const double irho = 1.0 / rho;
-  const double ise = 1.0 / fabs(b[SDC_NX - 1]);
-  int it = 1;
-  for (; it <= ctl.maxiter; ++it) {
+__device__ __forceinline__ int newton_fast(double* x, const double* b, double irho, double ise, double dtm,
+                                           ParamPtr P, double gm1, double tol, double tau, int it0, int itmax,
+                                           int& st) {
+  int it = it0;
+  for (; it <= itmax; ++it) {
     double G[SDC_NX];
     MT M[SDC_NNZ];
     net_residual_matrix<MT>(x, b, irho, dtm, P, gm1, G, M);
-    if (!net_lu<MT>(M, (MT)ctl.tau)) break;  // pivot guard: finish on the dense path
+    if (!net_lu<MT>(M, (MT)tau)) {
+      st = 2;
+      return it;
+    }
     MT r[SDC_NX];
 #pragma unroll
     for (int i = 0; i < SDC_NX; ++i) r[i] = (MT)(-G[i]);
@@ -544,10 +548,47 @@ __device__ __forceinline__ int newton_solve(double* x, const double* b, double r
       err = fmax(err, fabs(d) * (i == SDC_NX - 1 ? ise : irho));
       inf_or_nan += d * 0.0;
     }
-    if (!(inf_or_nan == 0.0)) return -1;  // a non-finite step never converges
-    if (err <= ctl.tol) return it;
+    if (!(inf_or_nan == 0.0)) {
+      st = 3;
+      return it;
+    }
+    if (err <= tol) {
+      st = 0;
+      return it;
+    }
   }
-  if (it > ctl.maxiter) return -1;
+  st = 1;
+  return itmax;
+}
+
+// Queue slot for lanes that defer their zone: one atomic per wavefront.
+__device__ __forceinline__ long long defer_slot(unsigned* count, bool want) {
+  const unsigned long long mask = __ballot(want);
+  if (mask == 0ull) return -1;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)mask) - 1;
+  unsigned base = 0u;
+  if (lane == leader) base = atomicAdd(count, (unsigned)__popcll(mask));
+  base = __shfl(base, leader, 64);
+  const unsigned rank = (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+  return want ? (long long)(base + rank) : -1;
+}
+
+// Finish a deferred solve: the fast pass from iteration it0 + 1 (it0 > 0) or
+// the dense pivoted Newton from iteration -it0 (it0 < 0, guard failure).
+template <class MT>
+__device__ __forceinline__ int newton_finish(double* x, const double* b, double rho, double dtm, ParamPtr P, double gm1,
+                                             const NewtonCtl& ctl, int it0, int& fallbacks) {
+  const double irho = 1.0 / rho;
+  const double ise = 1.0 / fabs(b[SDC_NX - 1]);
+  int start = -it0;
+  if (it0 > 0) {
+    int st = 1;
+    const int it = newton_fast<MT>(x, b, irho, ise, dtm, P, gm1, ctl.tol, ctl.tau, it0 + 1, ctl.maxiter, st);
+    if (st == 0) return it;
+    if (st != 2) return -1;
+    start = it;
+  }
   fallbacks = 1;
   VecX xv, bv;
 #pragma unroll
@@ -555,7 +596,7 @@ __device__ __forceinline__ int newton_solve(double* x, const double* b, double r
     xv.v[i] = x[i];
     bv.v[i] = b[i];
   }
-  const DenseResult r = dense_newton(xv, bv, rho, dtm, P, gm1, ctl.tol, it, ctl.maxiter);
+  const DenseResult r = dense_newton(xv, bv, rho, dtm, P, gm1, ctl.tol, start, ctl.maxiter);
 #pragma unroll
   for (int i = 0; i < SDC_NX; ++i) x[i] = r.x.v[i];
   return r.it;
@@ -574,19 +615,38 @@ template <class MT>
 __device__ __forceinline__ void reaction_solve_body(const SolveArgs& a) {
   const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = z < a.Z;
-  int nu = 0, fb = 0;
-  bool nonfinite = false;
+  ParamPtr P = (ParamPtr)a.P;
+  double x[SDC_NX], b[SDC_NX], rho = 1.0;
+  int it = 0, st = 3;
   if (valid) {
-    double x[SDC_NX], b[SDC_NX];
 #pragma unroll
     for (int i = 0; i < SDC_NX; ++i) {
       x[i] = a.x[(i64)i * a.Z + z];
       b[i] = a.b[(i64)i * a.Z + z];
     }
-    const double rho = a.rho[z];
-    nu = newton_solve<MT>(x, b, rho, a.dtm, (ParamPtr)a.P, a.gm1, a.ctl, fb);
+    rho = a.rho[z];
+    const double ise = 1.0 / fabs(b[SDC_NX - 1]);
+    it = newton_fast<MT>(x, b, 1.0 / rho, ise, a.dtm, P, a.gm1, a.ctl.tol, a.ctl.tau, 1,
+                         min(a.ctl.cap, a.ctl.maxiter), st);
+  }
+  const bool defer = valid && (st == 2 || (st == 1 && a.ctl.cap < a.ctl.maxiter));
+  const long long slot = defer_slot(a.q.count, defer);
+  int nu = 0;
+  bool nonfinite = false;
+  if (defer) {
+    const i64 cap = a.q.capacity;
+    a.q.z[slot] = z;
+    a.q.it[slot] = st == 2 ? -it : it;
+#pragma unroll
+    for (int i = 0; i < SDC_NX; ++i) {
+      a.q.x[(i64)i * cap + slot] = x[i];
+      a.q.b[(i64)i * cap + slot] = b[i];
+    }
+    a.q.aux[slot] = rho;
+  } else if (valid) {
+    nu = st == 0 ? it : -1;
     double R[SDC_NX];
-    net_source(x, 1.0 / rho, (ParamPtr)a.P, a.gm1, R);
+    net_source(x, 1.0 / rho, P, a.gm1, R);
 #pragma unroll
     for (int i = 0; i < SDC_NX; ++i) {
       a.x[(i64)i * a.Z + z] = x[i];
@@ -595,14 +655,54 @@ __device__ __forceinline__ void reaction_solve_body(const SolveArgs& a) {
     a.iters[z] = nu;
     nonfinite = !all_finite(x);
   }
+  stats_block(a.stats, nu, valid && !defer, nonfinite, 0);
+}
+
+template <class MT>
+__device__ __forceinline__ void reaction_finish_body(const SolveArgs& a) {
+  const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < (i64)*a.q.count;
+  ParamPtr P = (ParamPtr)a.P;
+  int nu = 0, fb = 0;
+  bool nonfinite = false;
+  if (valid) {
+    const i64 cap = a.q.capacity;
+    const i64 z = a.q.z[i];
+    double x[SDC_NX], b[SDC_NX];
+#pragma unroll
+    for (int k = 0; k < SDC_NX; ++k) {
+      x[k] = a.q.x[(i64)k * cap + i];
+      b[k] = a.q.b[(i64)k * cap + i];
+    }
+    const double rho = a.q.aux[i];
+    nu = newton_finish<MT>(x, b, rho, a.dtm, P, a.gm1, a.ctl, a.q.it[i], fb);
+    double R[SDC_NX];
+    net_source(x, 1.0 / rho, P, a.gm1, R);
+#pragma unroll
+    for (int k = 0; k < SDC_NX; ++k) {
+      a.x[(i64)k * a.Z + z] = x[k];
+      a.R[(i64)k * a.Z + z] = R[k];
+    }
+    a.iters[z] = nu;
+    nonfinite = !all_finite(x);
+  }
   stats_block(a.stats, nu, valid, nonfinite, fb);
 }
 
 #ifndef SDC_MIXED
-extern "C" __global__ __launch_bounds__(256) void sdc_reaction_solve(SolveArgs a) { reaction_solve_body<double>(a); }
+typedef double SdcMT;
 #else
-extern "C" __global__ __launch_bounds__(256) void sdc_reaction_solve(SolveArgs a) { reaction_solve_body<float>(a); }
+typedef float SdcMT;
 #endif
+// Two register budgets of the hot kernels: the compiler's choice (occupancy 1
+// for the larger networks) and one that targets two waves per SIMD; the
+// autotuner picks between them.
+#define SDC_OCC2 __attribute__((amdgpu_waves_per_eu(2, 2)))
+extern "C" __global__ __launch_bounds__(256) void sdc_reaction_solve(SolveArgs a) { reaction_solve_body<SdcMT>(a); }
+extern "C" __global__ __launch_bounds__(256) SDC_OCC2 void sdc_reaction_solve_o2(SolveArgs a) {
+  reaction_solve_body<SdcMT>(a);
+}
+extern "C" __global__ __launch_bounds__(256) void sdc_reaction_finish(SolveArgs a) { reaction_finish_body<SdcMT>(a); }
 
 // ---- R(U): the reactive source of a full state, on the reacting variables.
 
@@ -647,14 +747,34 @@ __device__ __forceinline__ constexpr int react_index(int c) {
   return c == 1 + SDC_DIM ? SDC_NX - 1 : (c >= SDC_NH ? c - SDC_NH : -1);
 }
 
+// Finalise node m+1 of zone z: rho, rho u from the explicit part, rho E =
+// x_e + KE, rho X = x_s, and R^{m+1} re-evaluated at the root.
+__device__ __forceinline__ void transition_store(const TransArgs& a, i64 z, double rho, double ke, const double* mom,
+                                                 const double* x, ParamPtr P) {
+  const i64 Z = a.Z;
+  double R[SDC_NX];
+  net_source(x, 1.0 / rho, P, a.gm1, R);
+  double* __restrict__ Uo = a.Uout;
+  Uo[z] = rho;
+#pragma unroll
+  for (int d = 0; d < SDC_DIM; ++d) Uo[(i64)(1 + d) * Z + z] = mom[d];
+  Uo[(i64)(1 + SDC_DIM) * Z + z] = x[SDC_NX - 1] + ke;
+#pragma unroll
+  for (int s = 0; s < SDC_NS; ++s) Uo[(i64)(SDC_NH + s) * Z + z] = x[s];
+#pragma unroll
+  for (int i = 0; i < SDC_NX; ++i) a.Rout[(i64)i * Z + z] = R[i];
+}
+
 template <class MT, int KIND>
 __device__ __forceinline__ void transition_body(const TransArgs& a) {
   const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = z < a.Z;
-  int nu = 0, fb = 0;
-  bool nonfinite = false;
+  ParamPtr P = (ParamPtr)a.P;
+  const i64 Z = a.Z;
+  double rho = 1.0, ke = 0.0, mom[SDC_DIM];
+  double b[SDC_NX], x[SDC_NX];
+  int it = 0, st = 3;
   if (valid) {
-    const i64 Z = a.Z;
     double rhs[SDC_NC];
     if (KIND == KIND_FIRST) {
 #pragma unroll
@@ -691,12 +811,13 @@ __device__ __forceinline__ void transition_body(const TransArgs& a) {
         rhs[c] = fma(a.dtm, a.Am[(i64)c * Z + z], a.Um[(i64)c * Z + z]) + a.Cin[(i64)c * Z + z];
     }
     // explicit part: rho and rho u are final
-    const double rho = rhs[0];
-    double ke = 0.0;
+    rho = rhs[0];
 #pragma unroll
-    for (int d = 0; d < SDC_DIM; ++d) ke = fma(rhs[1 + d], rhs[1 + d], ke);
+    for (int d = 0; d < SDC_DIM; ++d) {
+      mom[d] = rhs[1 + d];
+      ke = fma(rhs[1 + d], rhs[1 + d], ke);
+    }
     ke = 0.5 * ke / rho;
-    double b[SDC_NX], x[SDC_NX];
 #pragma unroll
     for (int s = 0; s < SDC_NS; ++s) b[s] = rhs[SDC_NH + s];
     b[SDC_NX - 1] = rhs[1 + SDC_DIM] - ke;
@@ -715,31 +836,79 @@ __device__ __forceinline__ void transition_body(const TransArgs& a) {
       for (int s = 0; s < SDC_NS; ++s) x[s] = g[(i64)(SDC_NH + s) * Z + z];
       x[SDC_NX - 1] = g[(i64)(1 + SDC_DIM) * Z + z] - gke;
     }
-    nu = newton_solve<MT>(x, b, rho, a.dtm, (ParamPtr)a.P, a.gm1, a.ctl, fb);
-    double R[SDC_NX];
-    net_source(x, 1.0 / rho, (ParamPtr)a.P, a.gm1, R);
-    double* __restrict__ Uo = a.Uout;
-    Uo[z] = rho;
+    it = newton_fast<MT>(x, b, 1.0 / rho, 1.0 / fabs(b[SDC_NX - 1]), a.dtm, P, a.gm1, a.ctl.tol, a.ctl.tau, 1,
+                         min(a.ctl.cap, a.ctl.maxiter), st);
+  }
+  const bool defer = valid && (st == 2 || (st == 1 && a.ctl.cap < a.ctl.maxiter));
+  const long long slot = defer_slot(a.q.count, defer);
+  int nu = 0;
+  bool nonfinite = false;
+  if (defer) {
+    const i64 cap = a.q.capacity;
+    a.q.z[slot] = z;
+    a.q.it[slot] = st == 2 ? -it : it;
 #pragma unroll
-    for (int d = 0; d < SDC_DIM; ++d) Uo[(i64)(1 + d) * Z + z] = rhs[1 + d];
-    Uo[(i64)(1 + SDC_DIM) * Z + z] = x[SDC_NX - 1] + ke;
+    for (int i = 0; i < SDC_NX; ++i) {
+      a.q.x[(i64)i * cap + slot] = x[i];
+      a.q.b[(i64)i * cap + slot] = b[i];
+    }
+    a.q.aux[slot] = rho;
+    a.q.aux[cap + slot] = ke;
 #pragma unroll
-    for (int s = 0; s < SDC_NS; ++s) Uo[(i64)(SDC_NH + s) * Z + z] = x[s];
+    for (int d = 0; d < SDC_DIM; ++d) a.q.aux[(i64)(2 + d) * cap + slot] = mom[d];
+  } else if (valid) {
+    nu = st == 0 ? it : -1;
+    transition_store(a, z, rho, ke, mom, x, P);
+    nonfinite = !all_finite(x);
+  }
+  stats_block(a.stats, nu, valid && !defer, nonfinite, 0);
+}
+
+template <class MT>
+__device__ __forceinline__ void transition_finish_body(const TransArgs& a) {
+  const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < (i64)*a.q.count;
+  ParamPtr P = (ParamPtr)a.P;
+  int nu = 0, fb = 0;
+  bool nonfinite = false;
+  if (valid) {
+    const i64 cap = a.q.capacity;
+    const i64 z = a.q.z[i];
+    double x[SDC_NX], b[SDC_NX], mom[SDC_DIM];
 #pragma unroll
-    for (int i = 0; i < SDC_NX; ++i) a.Rout[(i64)i * Z + z] = R[i];
+    for (int k = 0; k < SDC_NX; ++k) {
+      x[k] = a.q.x[(i64)k * cap + i];
+      b[k] = a.q.b[(i64)k * cap + i];
+    }
+    const double rho = a.q.aux[i], ke = a.q.aux[cap + i];
+#pragma unroll
+    for (int d = 0; d < SDC_DIM; ++d) mom[d] = a.q.aux[(i64)(2 + d) * cap + i];
+    nu = newton_finish<MT>(x, b, rho, a.dtm, P, a.gm1, a.ctl, a.q.it[i], fb);
+    transition_store(a, z, rho, ke, mom, x, P);
     nonfinite = !all_finite(x);
   }
   stats_block(a.stats, nu, valid, nonfinite, fb);
 }
 
-#ifndef SDC_MIXED
-typedef double SdcMT;
-#else
-typedef float SdcMT;
-#endif
 extern "C" __global__ __launch_bounds__(256) void sdc_transition_first(TransArgs a) { transition_body<SdcMT, KIND_FIRST>(a); }
 extern "C" __global__ __launch_bounds__(256) void sdc_transition_node0(TransArgs a) { transition_body<SdcMT, KIND_NODE0>(a); }
 extern "C" __global__ __launch_bounds__(256) void sdc_transition_later(TransArgs a) { transition_body<SdcMT, KIND_LATER>(a); }
+extern "C" __global__ __launch_bounds__(256) SDC_OCC2 void sdc_transition_first_o2(TransArgs a) {
+  transition_body<SdcMT, KIND_FIRST>(a);
+}
+extern "C" __global__ __launch_bounds__(256) SDC_OCC2 void sdc_transition_node0_o2(TransArgs a) {
+  transition_body<SdcMT, KIND_NODE0>(a);
+}
+extern "C" __global__ __launch_bounds__(256) SDC_OCC2 void sdc_transition_later_o2(TransArgs a) {
+  transition_body<SdcMT, KIND_LATER>(a);
+}
+extern "C" __global__ __launch_bounds__(256) void sdc_transition_finish(TransArgs a) { transition_finish_body<SdcMT>(a); }
+
+// reset of the deferred-zone counter (a kernel, so captured graphs stay valid)
+extern "C" __global__ void sdc_reset_counter(unsigned* c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0u;
+}
+
 
 // ---- constant fill (used instead of memset so that captured graphs stay valid)
 extern "C" __global__ __launch_bounds__(256) void sdc_fill(FillArgs a) {

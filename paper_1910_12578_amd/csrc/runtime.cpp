@@ -365,6 +365,15 @@ struct sdc_handle_s {
   // adjoint workspace (allocated on first use): forward replay nodes, stored
   // node states of every iteration, adjoint arrays, parameter partials
   std::vector<double*> adj_buf;
+  hipFunction_t f_first_o2 = nullptr, f_node0_o2 = nullptr, f_later_o2 = nullptr, f_trans_finish = nullptr,
+                f_solve_o2 = nullptr, f_solve_finish = nullptr, f_reset = nullptr;
+  // deferred-zone queue (capacity Z, allocated on first use) and the tuned
+  // kernel choice: occupancy-2 variants and the fast-pass iteration cap
+  DeferQueue q{};
+  bool q_ready = false;
+  int occ2 = 0;
+  int cap = 0;  // 0: no cap (newton_maxiter)
+  bool tuned = false;
   hipFunction_t f_advect = nullptr, f_advect3d = nullptr, f_source = nullptr, f_solve = nullptr, f_first = nullptr,
                 f_node0 = nullptr, f_later = nullptr, f_fill = nullptr;
   void* d_params = nullptr;
@@ -410,9 +419,12 @@ int kind_of(const sdc_handle h, hipFunction_t f) {
   if (f == h->f_advect || f == h->f_advect3d) return SDC_K_ADVECT;
   if (f == h->f_source) return SDC_K_SOURCE;
   if (f == h->f_solve) return SDC_K_SOLVE;
-  if (f == h->f_first) return SDC_K_TRANSITION_FIRST;
-  if (f == h->f_node0) return SDC_K_TRANSITION_NODE0;
-  if (f == h->f_later) return SDC_K_TRANSITION_LATER;
+  if (f == h->f_solve_o2) return SDC_K_SOLVE;
+  if (f == h->f_solve_finish || f == h->f_trans_finish) return SDC_K_FINISH;
+  if (f == h->f_first || f == h->f_first_o2) return SDC_K_TRANSITION_FIRST;
+  if (f == h->f_node0 || f == h->f_node0_o2) return SDC_K_TRANSITION_NODE0;
+  if (f == h->f_later || f == h->f_later_o2) return SDC_K_TRANSITION_LATER;
+  if (f == h->f_reset) return SDC_K_FILL;
   if (f == h->f_fill) return SDC_K_FILL;
   return SDC_K_ADJOINT;
 }
@@ -457,7 +469,40 @@ NewtonCtl newton_ctl(const sdc_handle h) {
   c.tol = h->P.cfg.newton_tol;
   c.tau = h->P.cfg.pivot_threshold;
   c.maxiter = h->P.cfg.newton_maxiter;
+  c.cap = h->cap > 0 ? h->cap : h->P.cfg.newton_maxiter;
   return c;
+}
+
+// Deferred-zone queue: capacity Z, so every zone can be deferred.
+int ensure_queue(sdc_handle h) {
+  if (h->q_ready) return SDC_OK;
+  const int64_t Z = h->P.Z;
+  DeferQueue& q = h->q;
+  q.capacity = Z;
+  const size_t aux = 2 + h->P.cfg.dim;
+  if (hipMalloc((void**)&q.z, Z * sizeof(sdc_i64)) != hipSuccess ||
+      hipMalloc((void**)&q.it, Z * sizeof(int)) != hipSuccess ||
+      hipMalloc((void**)&q.x, (size_t)h->nx * Z * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&q.b, (size_t)h->nx * Z * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&q.aux, aux * Z * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&q.count, sizeof(unsigned)) != hipSuccess)
+    return fail(h, SDC_ERR_NOMEM, "hipMalloc(deferred-zone queue) failed");
+  h->q_ready = true;
+  return SDC_OK;
+}
+
+void free_queue(sdc_handle h) {
+  DeferQueue& q = h->q;
+  for (void* p : {(void*)q.z, (void*)q.it, (void*)q.x, (void*)q.b, (void*)q.aux, (void*)q.count})
+    if (p) (void)hipFree(p);
+  h->q = DeferQueue{};
+  h->q_ready = false;
+}
+
+int reset_queue(sdc_handle h, hipStream_t s) {
+  void* params[] = {&h->q.count};
+  HIP_CHECK(h, hipModuleLaunchKernel(h->f_reset, 1, 1, 1, 64, 1, 1, 0, s, params, nullptr));
+  return SDC_OK;
 }
 
 int advect(sdc_handle h, const double* U, double* A, hipStream_t s) {
@@ -508,6 +553,7 @@ bool nodes_ok(const sdc_handle h, const sdc_nodes* n, bool need_c) {
 // One iteration k -> k+1 over the M transitions, then A at node M.
 int sweep(sdc_handle h, double dt, int k, const sdc_nodes& n, hipStream_t s) {
   const int M = h->M;
+  if (int rc = ensure_queue(h)) return rc;
   for (int m = 0; m < M; ++m) {
     TransArgs a;
     std::memset(&a, 0, sizeof a);
@@ -536,9 +582,13 @@ int sweep(sdc_handle h, double dt, int k, const sdc_nodes& n, hipStream_t s) {
     a.gm1 = h->P.cfg.gamma - 1.0;
     a.ctl = newton_ctl(h);
     a.stats = h->d_stats;
-    hipFunction_t f = k == 0 ? h->f_first : (m == 0 ? h->f_node0 : h->f_later);
-    int rc = launch(h, f, h->P.Z, &a, s);
+    a.q = h->q;
+    hipFunction_t f = k == 0 ? (h->occ2 ? h->f_first_o2 : h->f_first)
+                             : (m == 0 ? (h->occ2 ? h->f_node0_o2 : h->f_node0) : (h->occ2 ? h->f_later_o2 : h->f_later));
+    int rc = reset_queue(h, s);
     if (rc) return rc;
+    if ((rc = launch(h, f, h->P.Z, &a, s))) return rc;
+    if ((rc = launch(h, h->f_trans_finish, h->P.Z, &a, s))) return rc;
     if (h->P.cfg.advection) {
       rc = advect(h, n.U[m + 1], n.A[m + 1], s);
       if (rc) return rc;
@@ -559,6 +609,7 @@ void drop_graphs(sdc_handle h) {
 // Capture the K sweeps of one step with node 0 in n.U[0] into an executable
 // graph.  Capture runs on the handle's own stream: nothing executes.
 int capture_step(sdc_handle h, double dt, const sdc_nodes& n, hipGraphExec_t* out) {
+  if (int rc = ensure_queue(h)) return rc;  // no allocation while capturing
   if (!h->capture_stream) HIP_CHECK(h, hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
   HIP_CHECK(h, hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
   int rc = SDC_OK;
@@ -738,6 +789,82 @@ int step_adjoint(sdc_handle h, double dt, const double* Un, const double* Ubar1,
   return theta_reduce(h, W.part, thetabar, s);
 }
 
+// ---- autotuning of the Newton schedule
+std::string tune_path(const sdc_handle h) {
+  const sdc_config& c = h->P.cfg;
+  char name[128];
+  std::snprintf(name, sizeof name, "tune_%016llx_z%lld_k%d_a%d.txt", (unsigned long long)fnv1a(h->P.source),
+                (long long)h->P.Z, (int)c.n_iters, (int)c.advection);
+  return cache_dir() + "/" + name;
+}
+
+bool load_tuning(sdc_handle h) {
+  std::ifstream f(tune_path(h));
+  int o = -1, c = -1;
+  if (!(f >> o >> c) || o < 0 || o > 1 || c < 0) return false;
+  h->occ2 = o;
+  h->cap = c;
+  h->tuned = true;
+  return true;
+}
+
+int autotune(sdc_handle h, double dt, const double* U, const sdc_nodes& n, hipStream_t s) {
+  const int64_t zc = (int64_t)h->nc * h->P.Z;
+  int rc = ensure_queue(h);
+  if (rc) return rc;
+  unsigned long long saved[SDC_NSTATS];
+  HIP_CHECK(h, hipStreamSynchronize(s));
+  HIP_CHECK(h, hipMemcpy(saved, h->d_stats, sizeof saved, hipMemcpyDeviceToHost));
+  HIP_CHECK(h, hipMemcpyAsync(n.U[0], U, zc * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if ((rc = advect(h, n.U[0], n.A[0], s)) || (rc = source(h, n.U[0], n.R[0], s))) return rc;
+  if (!h->P.cfg.advection)
+    for (int j = 1; j <= h->M; ++j)
+      if ((rc = fill(h, n.A[j], zc, 0.0, s))) return rc;
+  const bool prof = h->profile;
+  h->profile = false;
+  hipEvent_t e0, e1;
+  HIP_CHECK(h, hipEventCreate(&e0));
+  HIP_CHECK(h, hipEventCreate(&e1));
+  const int caps[] = {0, 4, 5, 6};
+  float best = 1e30f;
+  int bo = 0, bc = 0;
+  for (int rep = 0; rep < 2 && rc == SDC_OK; ++rep)  // the first pass warms caches and clocks
+    for (int o = 0; o < 2 && rc == SDC_OK; ++o)
+      for (int c : caps) {
+        h->occ2 = o;
+        h->cap = c;
+        if ((rc = (hipEventRecord(e0, s) == hipSuccess ? SDC_OK : SDC_ERR_HIP))) break;
+        for (int k = 0; k < h->P.cfg.n_iters && rc == SDC_OK; ++k) rc = sweep(h, dt, k, n, s);
+        if (rc) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          rc = fail(h, SDC_ERR_HIP, "autotune event failed");
+          break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep == 1 && ms < best) {
+          best = ms;
+          bo = o;
+          bc = c;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->profile = prof;
+  if (rc) return rc;
+  h->occ2 = bo;
+  h->cap = bc;
+  h->tuned = true;
+  drop_graphs(h);
+  HIP_CHECK(h, hipMemcpy(h->d_stats, saved, sizeof saved, hipMemcpyHostToDevice));
+  const std::string path = tune_path(h);
+  std::string text = std::to_string(bo) + " " + std::to_string(bc) + "\n";
+  std::vector<char> data(text.begin(), text.end());
+  const auto k = path.rfind('/');
+  write_file_atomic(path.substr(0, k), path.substr(k + 1), data);
+  return SDC_OK;
+}
+
 int check_handle(sdc_handle h) {
   if (!h) return fail(nullptr, SDC_ERR_ARG, "null handle");
   return SDC_OK;
@@ -767,6 +894,7 @@ int sdc_config_default(sdc_config* cfg) {
   cfg->nbox = 0;
   cfg->box_n = nullptr;
   cfg->graph = 0;
+  cfg->autotune = 0;
   return SDC_OK;
 }
 
@@ -837,7 +965,10 @@ int sdc_init(const sdc_config* cfg, const sdc_network* net, sdc_handle* out) {
              {&h->f_fill, "sdc_fill"}, {&h->f_advect_vjp, "sdc_advect_vjp"},
              {&h->f_trans_adj_first, "sdc_transition_adjoint_first"}, {&h->f_trans_adj, "sdc_transition_adjoint"},
              {&h->f_source_vjp, "sdc_source_vjp"}, {&h->f_theta_reduce, "sdc_theta_reduce"},
-             {&h->f_axpy, "sdc_axpy"}};
+             {&h->f_axpy, "sdc_axpy"}, {&h->f_first_o2, "sdc_transition_first_o2"},
+             {&h->f_node0_o2, "sdc_transition_node0_o2"}, {&h->f_later_o2, "sdc_transition_later_o2"},
+             {&h->f_trans_finish, "sdc_transition_finish"}, {&h->f_solve_o2, "sdc_reaction_solve_o2"},
+             {&h->f_solve_finish, "sdc_reaction_finish"}, {&h->f_reset, "sdc_reset_counter"}};
   for (auto& fn : fns) {
     e = hipModuleGetFunction(fn.f, h->mod, fn.name);
     if (e != hipSuccess) return bail(SDC_ERR_HIP, std::string("missing kernel ") + fn.name);
@@ -894,6 +1025,7 @@ int sdc_destroy(sdc_handle h) {
   drop_graphs(h);
   if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
   for (double* p : h->adj_buf) (void)hipFree(p);
+  free_queue(h);
   if (h->d_params) (void)hipFree(h->d_params);
   if (h->d_box_off) (void)hipFree(h->d_box_off);
   if (h->d_box_ext) (void)hipFree(h->d_box_ext);
@@ -949,7 +1081,12 @@ int sdc_reaction_solve(sdc_handle h, double dt_m, const double* rho, const doubl
   a.gm1 = h->P.cfg.gamma - 1.0;
   a.ctl = newton_ctl(h);
   a.stats = h->d_stats;
-  return launch(h, h->f_solve, h->P.Z, &a, (hipStream_t)stream);
+  if (int rc = ensure_queue(h)) return rc;
+  a.q = h->q;
+  hipStream_t s = (hipStream_t)stream;
+  if (int rc = reset_queue(h, s)) return rc;
+  if (int rc = launch(h, h->occ2 ? h->f_solve_o2 : h->f_solve, h->P.Z, &a, s)) return rc;
+  return launch(h, h->f_solve_finish, h->P.Z, &a, s);
 }
 
 int sdc_sweep(sdc_handle h, double dt, int32_t k, const sdc_nodes* nodes, void* stream) {
@@ -973,6 +1110,8 @@ int sdc_step(sdc_handle h, double dt, int32_t nsteps, double* U, const sdc_nodes
   h->last_stream = s;
   sdc_nodes n = *work;
   const size_t bytesU = (size_t)h->nc * h->P.Z * sizeof(double);
+  if (h->P.cfg.autotune && !h->tuned && !load_tuning(h))
+    if (int rc = autotune(h, dt, U, n, s)) return rc;
   HIP_CHECK(h, hipMemcpyAsync(n.U[0], U, bytesU, hipMemcpyDeviceToDevice, s));
   int rc = advect(h, n.U[0], n.A[0], s);
   if (rc) return rc;
@@ -1037,6 +1176,33 @@ int sdc_step_adjoint(sdc_handle h, double dt, const double* U_n, const double* U
   hipStream_t s = (hipStream_t)stream;
   h->last_stream = s;
   return step_adjoint(h, dt, U_n, Ubar_np1, Ubar_n, thetabar, s);
+}
+
+int sdc_set_schedule(sdc_handle h, int32_t occ2, int32_t cap) {
+  if (int rc = check_handle(h)) return rc;
+  if (occ2 < 0 || occ2 > 1 || cap < 0) return fail(h, SDC_ERR_ARG, "occ2 must be 0 or 1 and cap >= 0");
+  h->occ2 = occ2;
+  h->cap = cap;
+  h->tuned = true;
+  drop_graphs(h);
+  return SDC_OK;
+}
+
+int sdc_get_schedule(sdc_handle h, int32_t* occ2, int32_t* cap) {
+  if (int rc = check_handle(h)) return rc;
+  if (occ2) *occ2 = h->occ2;
+  if (cap) *cap = h->cap;
+  return SDC_OK;
+}
+
+int sdc_autotune(sdc_handle h, double dt, const double* U, const sdc_nodes* work, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!U || !work) return fail(h, SDC_ERR_ARG, "null U or work");
+  if (!std::isfinite(dt) || dt <= 0.0) return fail(h, SDC_ERR_ARG, "dt must be positive");
+  if (!nodes_ok(h, work, h->P.cfg.n_iters >= 2 && h->M >= 2)) return fail(h, SDC_ERR_ARG, "missing node arrays");
+  hipStream_t s = (hipStream_t)stream;
+  h->last_stream = s;
+  return autotune(h, dt, U, *work, s);
 }
 
 int sdc_stats(sdc_handle h, int64_t* out) {

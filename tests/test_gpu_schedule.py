@@ -1,0 +1,110 @@
+"""Kernel schedules of the Newton solves (register budget, fast-pass iteration
+cap with a deferred-zone finish kernel) and the autotuner that picks one.
+
+The schedule only changes where a zone's Newton iterations run, not their
+arithmetic, so every schedule must give the same bits as the default one, and
+the default one matches the oracle (paper Sec. 2, Eq. 2).
+"""
+import numpy as np
+import pytest
+
+from oracle import sdc as osdc
+from tests.helpers import TOL_FP64, rel_err_per_component, to_gpu, to_np
+from tests.test_gpu_parity import make
+
+pytestmark = pytest.mark.gpu
+
+SCHEDULES = [(1, 0), (0, 1), (1, 2), (0, 3), (1, 4), (0, 6)]
+
+
+def one_step(h, w, nsteps=1):
+    nc = w["U0"].shape[0]
+    U = to_gpu(w["U0"].reshape(nc, -1))
+    h.stats_reset()
+    h.step(w["dt"], nsteps, U)
+    return U, h.stats()
+
+
+@pytest.mark.parametrize("name", ["net2d", "net3d"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_step_schedules_bitwise_identical(name, precision):
+    w, prob, h = make(name, precision=precision)
+    ref, sref = one_step(h, w, 2)
+    for occ2, cap in SCHEDULES:
+        h.set_schedule(occ2, cap)
+        assert h.schedule() == (occ2, cap)
+        U, s = one_step(h, w, 2)
+        print(f"{name} p{precision} occ2={occ2} cap={cap}: identical={bool((U == ref).all())}")
+        assert bool((U == ref).all()), (occ2, cap)
+        assert s == sref, (occ2, cap)
+
+
+@pytest.mark.parametrize("cap", [1, 2, 5])
+def test_reaction_solve_schedules_bitwise_identical(cap):
+    w, prob, h = make("net2d")
+    rho, _, x0, _ = osdc.split_state(w["U0"], prob)
+    b = x0 * (1.0 + 0.05 * np.cos(np.arange(x0.size)).reshape(x0.shape))
+    dtm = 2.0 * w["dt"]
+    xr, Rr, nr = h.reaction_solve(dtm, to_gpu(rho), to_gpu(b), to_gpu(x0))
+    for occ2 in (0, 1):
+        h.set_schedule(occ2, cap)
+        x, R, nu = h.reaction_solve(dtm, to_gpu(rho), to_gpu(b), to_gpu(x0))
+        assert bool((x == xr).all()) and bool((R == Rr).all()) and bool((nu == nr).all())
+
+
+def test_pivot_fallback_through_the_finish_kernel():
+    """With a cap every guard failure is finished by the dense pivoted Newton
+    in the second kernel; the result still matches the oracle."""
+    w, prob, h = make("net2d", pivot_threshold=2.0)
+    h.set_schedule(1, 2)
+    U0 = w["U0"]
+    nc = U0.shape[0]
+    Ug = to_gpu(U0.reshape(nc, -1))
+    h.step(w["dt"], 1, Ug)
+    ref = osdc.run(U0, w["dt"], 1, prob).reshape(nc, -1)
+    e = rel_err_per_component(to_np(Ug), ref)
+    assert np.all(e <= TOL_FP64), e
+    s = h.stats()
+    assert s["fallbacks"] == s["solves"] and s["failed"] == 0
+
+
+def test_unconverged_zones_with_cap():
+    w, prob, h = make("net2d", newton_maxiter=2)
+    rho, _, x0, _ = osdc.split_state(w["U0"], prob)
+    def solve():  # x is the initial iterate and is overwritten: a fresh copy per call
+        return h.reaction_solve(3 * w["dt"], to_gpu(rho), to_gpu(x0 * 1.01), to_gpu(x0))
+    xr, Rr, nr = solve()
+    sr = h.stats()
+    h.stats_reset()
+    h.set_schedule(0, 1)
+    x, R, nu = solve()
+    assert bool((x == xr).all()) and bool((nu == nr).all())
+    assert h.stats() == sr
+
+
+def test_bad_schedule_raises():
+    from paper_1910_12578_amd import SDCError
+    w, prob, h = make("chain1d")
+    with pytest.raises(SDCError):
+        h.set_schedule(2, 0)
+    with pytest.raises(SDCError):
+        h.set_schedule(0, -1)
+
+
+def test_autotune_keeps_results_and_stats():
+    w, prob, h = make("net2d")
+    ref, sref = one_step(h, w)
+    nc = w["U0"].shape[0]
+    U = to_gpu(w["U0"].reshape(nc, -1))
+    h.stats_reset()
+    occ2, cap = h.autotune(w["dt"], U)
+    print(f"autotuned schedule: occ2={occ2} cap={cap}")
+    assert occ2 in (0, 1) and cap in (0, 4, 5, 6)
+    assert h.stats()["solves"] == 0
+    assert bool((U == to_gpu(w["U0"].reshape(nc, -1))).all())  # input untouched
+    U2, s2 = one_step(h, w)
+    assert bool((U2 == ref).all()) and s2 == sref
+    _, _, ha = make("net2d", autotune=1)  # tunes on its first step (or reads the cached choice)
+    U3, s3 = one_step(ha, w)
+    assert bool((U3 == ref).all()) and s3 == sref
+    assert ha.schedule()[0] in (0, 1)
