@@ -40,6 +40,9 @@ typedef struct {
   const sdc_i64* box_off;
   const int* box_ext;
   const int* blk_box;
+  // row kernel (3D): complete x-rows per 256-thread block, z planes per chunk
+  int rows;
+  int zchunk;
 } AdvArgs;
 
 typedef struct {

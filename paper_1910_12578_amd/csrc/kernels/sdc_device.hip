@@ -61,18 +61,35 @@ __device__ __forceinline__ void stats_block(unsigned long long* __restrict__ sta
   if (threadIdx.x < SDC_NSTAT && sh[threadIdx.x] != 0u) atomicAdd(&stats[threadIdx.x], (u64)sh[threadIdx.x]);
 }
 
+// ------------------------------------------------------------ parameters
+// Copy the network parameters (NetParams, a flat array of doubles) from
+// device memory into LDS.  Every thread of the block must call it before any
+// divergence: it ends with a barrier.
+__device__ __forceinline__ ParamPtr stage_params(const void* gp) {
+  __shared__ NetParams sh_params;
+  const double* src = (const double*)gp;
+  double* dst = (double*)&sh_params;
+  for (int i = threadIdx.x; i < (int)(sizeof(NetParams) / sizeof(double)); i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
+  return (ParamPtr)&sh_params;
+}
+
 // ------------------------------------------------------------ advection
 // A(U) = -sum_d (F_{i+1/2} - F_{i-1/2}) / dx_d: method of lines, piecewise-
 // linear reconstruction of the conserved variables (central or monotonized-
 // central slopes), Rusanov face flux with the local max(|u_d| + c) of the two
 // face states or a frozen speed, periodic grid.
 
-__device__ __forceinline__ double slope_of(double um, double u0, double up, int slope) {
-  if (slope == 0) return 0.5 * (up - um);
+// Written with selects rather than branches: 2 min(|a|, |b|) equals
+// min(2|a|, 2|b|) exactly, and the sign comes from a.
+__device__ __forceinline__ double mc_slope_of(double um, double u0, double up) {
   const double a = u0 - um, b = up - u0;
-  if (!(a * b > 0.0)) return 0.0;
-  const double m = fmin(fmin(2.0 * fabs(a), 2.0 * fabs(b)), 0.5 * fabs(a + b));
-  return a > 0.0 ? m : -m;
+  const double m = fmin(2.0 * fmin(fabs(a), fabs(b)), 0.5 * fabs(a + b));
+  return a * b > 0.0 ? copysign(m, a) : 0.0;
+}
+
+__device__ __forceinline__ double slope_of(double um, double u0, double up, int slope) {
+  return slope == 0 ? 0.5 * (up - um) : mc_slope_of(um, u0, up);
 }
 
 // Face state pair (left/right of one face) of the hydro components.
@@ -204,16 +221,6 @@ extern "C" __global__ __launch_bounds__(256) void sdc_advect(AdvArgs a) {
   }
 }
 
-#if SDC_DIM == 3
-// ---- 3D advective term, z-marching.  A block of 64 x 4 threads owns a 64 x 4
-// column tile and walks SDC_ZCHUNK planes in z.  Plane k of every component is
-// staged in LDS with a two-zone x/y halo for the x and y stencils; each thread
-// carries its column's z window (U_k, U_{k+1}, the z slope at k and the flux
-// through face k-1/2) in registers, so every value crosses HBM about once.
-#define ZT_X 64
-#define ZT_Y 4
-#define SDC_ZCHUNK 32
-
 // Rusanov flux of the hydro components through one face from the two
 // reconstructed states, plus the face data the species fluxes need.
 __device__ __forceinline__ void hydro_face(const double* WL, const double* WR, int d, double gamma, double alpha,
@@ -230,181 +237,203 @@ __device__ __forceinline__ double species_face(double L, double R, const FaceHyd
   return 0.5 * (L * f.uL + R * f.uR) - 0.5 * f.a * (R - L);
 }
 
-// Species are processed in groups of up to SDC_SPG per block (the group index
-// is part of the grid): every group recomputes the hydro faces, which costs
-// re-reading the few hydro components but keeps the carried z windows small.
-#define SDC_SPG (SDC_NS < 5 ? SDC_NS : 5)
-#define SDC_NGRP ((SDC_NS + SDC_SPG - 1) / SDC_SPG)
-#define SDC_TC (SDC_NH + SDC_SPG)  // components staged per block
+#if SDC_DIM == 3
+// ---- 3D advective term: complete x-rows per block, marching in z.
+// A 256-thread block holds R = 256 / n0 complete x-rows, periodic in x, so
+// every x-face flux is computed once (by the zone to its right) and handed to
+// the zone on its left through LDS.  Each row marches up a chunk of planes in
+// z carrying, per component, the left state of the face above the current
+// plane and the flux through the face below it, so z-faces are computed once
+// as well.  The y stencil (both faces of a zone) is read from memory, where
+// the neighbouring rows of the same plane sit in L2.  Offsets inside one
+// component array are 32-bit byte offsets (the host guarantees 8 Z < 2^32).
+// Loads and stores through one buffer resource per array: 32-bit byte
+// offsets, the component's offset in a scalar register (the host guarantees
+// that every array is below 4 GiB), and out-of-range accesses return zero
+// instead of faulting.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t array_rsrc(const double* p, i64 bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)(unsigned)bytes, 0x00020000);
+}
 
-extern "C" __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void sdc_advect3d(AdvArgs a) {
-  __shared__ double tile[SDC_TC][ZT_Y + 4][ZT_X + 4];
+__device__ __forceinline__ double ld_at(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+typedef unsigned u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
+
+__device__ __forceinline__ void st_at(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+
+__device__ __forceinline__ int wrap_index(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+template <int SLOPE>
+__device__ __forceinline__ double slope_t(double um, double u0, double up) {
+  return SLOPE == 0 ? 0.5 * (up - um) : mc_slope_of(um, u0, up);
+}
+
+template <int SLOPE>
+__device__ __forceinline__ void advect_rows_body(const AdvArgs& a) {
+  __shared__ double sh_u[SDC_NH][256];   // hydro components of the current plane
+  __shared__ double sh_fh[SDC_NH][256];  // hydro x-face fluxes
+  __shared__ double sh_s[256];           // one species component
+  __shared__ double sh_fs[256];          // its x-face flux
   const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
-  const int tx = threadIdx.x % ZT_X, ty = threadIdx.x / ZT_X;
-  const int nbx = (n0 + ZT_X - 1) / ZT_X, nby = (n1 + ZT_Y - 1) / ZT_Y;
-  const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
-  const int grp = (int)(lb % SDC_NGRP);
-  const unsigned tb = lb / SDC_NGRP;
-  const int bx = (int)(tb % nbx), by = (int)((tb / nbx) % nby), bz = (int)(tb / (nbx * nby));
-  const int i = bx * ZT_X + tx, j = by * ZT_Y + ty;
-  const bool active = i < n0 && j < n1;
-  const int z0 = bz * SDC_ZCHUNK;
-  const int z1 = min(z0 + SDC_ZCHUNK, n2);
-  // 32-bit element offsets inside one component array (the host checks Z < 2^28):
-  // loads then take a uniform base plus a 32-bit per-lane offset
-  const int P = n0 * n1;
-  const i64 Z = a.Z;
-  const double* __restrict__ U = a.U;
-  // A tile position past the grid edge holds the periodic image of the grid
-  // (coordinates mod n), so every halo slot is the periodic neighbour of the
-  // zones next to it, also in ragged tiles; such positions compute but never store.
-  auto pmod = [](int v, int n) { return ((v % n) + n) % n; };
-  auto wrap = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
-  const int ic = pmod(i, n0), jc = pmod(j, n1);
-  const int col = jc * n0 + ic;
-  const int hy_row = ty < 2 ? by * ZT_Y - 2 + ty : by * ZT_Y + ZT_Y + (ty - 2);
-  const int hy = pmod(hy_row, n1) * n0 + ic;
-  const int hy_slot = ty < 2 ? ty : ZT_Y + 2 + (ty - 2);
-  const bool hx_on = tx < 2 || tx >= ZT_X - 2;
-  const int hx_colg = tx < 2 ? bx * ZT_X - 2 + tx : bx * ZT_X + ZT_X + (tx - (ZT_X - 2));
-  const int hx = jc * n0 + pmod(hx_colg, n0);
-  const int hx_slot = tx < 2 ? tx : ZT_X + 2 + (tx - (ZT_X - 2));
-  const double idx = a.idx[0], idy = a.idx[1], idz = a.idx[2];
-  // component of slot t: hydro first, then this block's species
-  auto comp = [&](int t) { return t < SDC_NH ? t : SDC_NH + grp * SDC_SPG + (t - SDC_NH); };
-  auto valid = [&](int t) { return t < SDC_NH || grp * SDC_SPG + (t - SDC_NH) < SDC_NS; };
-
-  double Uk[SDC_TC], Uk1[SDC_TC], dUk[SDC_TC], Fm[SDC_TC];
-  {
-    const int pm2 = wrap(z0 - 2, n2) * P, pm1 = wrap(z0 - 1, n2) * P;
-    const int p0 = z0 * P, p1 = wrap(z0 + 1, n2) * P;
-    double Wm[SDC_TC], WL[SDC_NH], WR[SDC_NH];
+  const int R = a.rows, ZC = a.zchunk;
+  const int t = threadIdx.x;
+  const int r = t / n0, x = t - r * n0;
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  const long long nslot = (long long)n1 * ((n2 + ZC - 1) / ZC);
+  const long long slot = (long long)b * R + r;
+  const bool row_ok = r < R && slot < nslot;
+  const int y = row_ok ? (int)(slot % n1) : 0;
+  const int k0 = row_ok ? (int)(slot / n1) * ZC : 0;
+  const int k1 = row_ok ? min(k0 + ZC, n2) : 0;
+  // LDS slots of the x neighbours; idle lanes (r >= R) only touch their own slot
+  const int rb = (r < R ? r : 0) * n0, xx = r < R ? x : 0;
+  const int lxm2 = r < R ? rb + wrap_index(xx - 2, n0) : t;
+  const int lxm1 = r < R ? rb + wrap_index(xx - 1, n0) : t;
+  const int lxp1 = r < R ? rb + wrap_index(xx + 1, n0) : t;
+  const unsigned P8 = (unsigned)n0 * (unsigned)n1 * 8u;  // plane stride in bytes
+  const unsigned row8 = ((unsigned)y * (unsigned)n0 + (unsigned)xx) * 8u;
+  unsigned oy[4];  // byte offsets of rows y-2, y-1, y+1, y+2 relative to row y
 #pragma unroll
-    for (int t = 0; t < SDC_TC; ++t) {
-      const double* Uc = U + (i64)(valid(t) ? comp(t) : 0) * Z;
-      const double um2 = Uc[pm2 + col], um1 = Uc[pm1 + col];
-      Uk[t] = Uc[p0 + col];
-      Uk1[t] = Uc[p1 + col];
-      const double dm1 = slope_of(um2, um1, Uk[t], a.slope);
-      dUk[t] = slope_of(um1, Uk[t], Uk1[t], a.slope);
-      Wm[t] = um1 + 0.5 * dm1;
-    }
+  for (int j = 0; j < 4; ++j) {
+    const int dy = j < 2 ? j - 2 : j - 1;
+    oy[j] = (unsigned)((wrap_index(y + dy, n1) - y) * n0) * 8u;
+  }
+  const i64 Z = a.Z;
+  const __amdgpu_buffer_rsrc_t rU = array_rsrc(a.U, (i64)SDC_NC * Z * 8);
+  const __amdgpu_buffer_rsrc_t rA = array_rsrc(a.A, (i64)SDC_NC * Z * 8);
+  const unsigned Z8 = (unsigned)Z * 8u;  // component stride in bytes
+  const double idx = a.idx[0], idy = a.idx[1], idz = a.idx[2];
+
+  // prologue: the face below plane k0 and the left state of the face above it
+  double WLz[SDC_NC], Fz[SDC_NC];
+  {
+    const unsigned o0 = (unsigned)wrap_index(k0 - 2, n2) * P8 + row8, o1 = (unsigned)wrap_index(k0 - 1, n2) * P8 + row8;
+    const unsigned o2 = (unsigned)k0 * P8 + row8, o3 = (unsigned)wrap_index(k0 + 1, n2) * P8 + row8;
+    double WL[SDC_NH], WR[SDC_NH];
 #pragma unroll
     for (int q = 0; q < SDC_NH; ++q) {
-      WL[q] = Wm[q];
-      WR[q] = Uk[q] - 0.5 * dUk[q];
+      const unsigned so = (unsigned)q * Z8;
+      const double v0 = ld_at(rU, o0, so), v1 = ld_at(rU, o1, so), v2 = ld_at(rU, o2, so), v3 = ld_at(rU, o3, so);
+      const double sA = slope_t<SLOPE>(v0, v1, v2), sB = slope_t<SLOPE>(v1, v2, v3);
+      WL[q] = v1 + 0.5 * sA;
+      WR[q] = v2 - 0.5 * sB;
+      WLz[q] = v2 + 0.5 * sB;
     }
-    FaceHydro f;
-    hydro_face(WL, WR, 2, a.gamma, a.alpha, Fm, f);
+    FaceHydro fzm;
+    hydro_face(WL, WR, 2, a.gamma, a.alpha, Fz, fzm);
 #pragma unroll
-    for (int t = SDC_NH; t < SDC_TC; ++t) Fm[t] = species_face(Wm[t], Uk[t] - 0.5 * dUk[t], f);
+    for (int s = 0; s < SDC_NS; ++s) {
+      const unsigned so = (unsigned)(SDC_NH + s) * Z8;
+      const double v0 = ld_at(rU, o0, so), v1 = ld_at(rU, o1, so), v2 = ld_at(rU, o2, so), v3 = ld_at(rU, o3, so);
+      const double sA = slope_t<SLOPE>(v0, v1, v2), sB = slope_t<SLOPE>(v1, v2, v3);
+      Fz[SDC_NH + s] = species_face(v1 + 0.5 * sA, v2 - 0.5 * sB, fzm);
+      WLz[SDC_NH + s] = v2 + 0.5 * sB;
+    }
   }
 
-  for (int k = z0; k < z1; ++k) {
-    const int pk = k * P, p2 = wrap(k + 2, n2) * P;
-#pragma unroll
-    for (int t = 0; t < SDC_TC; ++t) {
-      const double* Uc = U + (i64)(valid(t) ? comp(t) : 0) * Z;
-      tile[t][ty + 2][tx + 2] = Uk[t];
-      tile[t][hy_slot][tx + 2] = Uc[pk + hy];
-      if (hx_on) tile[t][ty + 2][hx_slot] = Uc[pk + hx];
-    }
-    __syncthreads();
-    double acc[SDC_NH];
-    FaceHydro fx[2], fy[2], fz;
+  // the trip count is the same for every thread of the block (barriers)
+  for (int k = k0; k < k0 + ZC; ++k) {
+    const bool act = row_ok && k < k1;
+    const int kc = k < n2 ? k : k - n2;
+    const unsigned oc = (unsigned)kc * P8 + row8;
+    const unsigned oz1 = (unsigned)wrap_index(kc + 1, n2) * P8 + row8;
+    const unsigned oz2 = (unsigned)wrap_index(kc + 2, n2) * P8 + row8;
+    // ---- hydro: y and z faces from memory, stage the plane for x
+    double Ay[SDC_NH], Az[SDC_NH];
+    FaceHydro fy0, fy1, fz, fx;
     {
-      double WL[2][SDC_NH], WR[2][SDC_NH];
+      double WLy0[SDC_NH], WRy0[SDC_NH], WLy1[SDC_NH], WRy1[SDC_NH], WRz[SDC_NH], WLzn[SDC_NH];
 #pragma unroll
       for (int q = 0; q < SDC_NH; ++q) {
-        const double* r = &tile[q][ty + 2][tx];
-        const double sm = slope_of(r[0], r[1], r[2], a.slope);
-        const double s0 = slope_of(r[1], r[2], r[3], a.slope);
-        const double sp = slope_of(r[2], r[3], r[4], a.slope);
-        WL[0][q] = r[1] + 0.5 * sm;
-        WR[0][q] = r[2] - 0.5 * s0;
-        WL[1][q] = r[2] + 0.5 * s0;
-        WR[1][q] = r[3] - 0.5 * sp;
+        const unsigned so = (unsigned)q * Z8;
+        const double c = ld_at(rU, oc, so);
+        sh_u[q][t] = c;
+        const double ym2 = ld_at(rU, oc + oy[0], so), ym1 = ld_at(rU, oc + oy[1], so);
+        const double yp1 = ld_at(rU, oc + oy[2], so), yp2 = ld_at(rU, oc + oy[3], so);
+        const double z1 = ld_at(rU, oz1, so), z2 = ld_at(rU, oz2, so);
+        const double sm = slope_t<SLOPE>(ym2, ym1, c), s0 = slope_t<SLOPE>(ym1, c, yp1);
+        const double sp = slope_t<SLOPE>(c, yp1, yp2), s1 = slope_t<SLOPE>(c, z1, z2);
+        WLy0[q] = ym1 + 0.5 * sm;
+        WRy0[q] = c - 0.5 * s0;
+        WLy1[q] = c + 0.5 * s0;
+        WRy1[q] = yp1 - 0.5 * sp;
+        WRz[q] = z1 - 0.5 * s1;
+        WLzn[q] = z1 + 0.5 * s1;
       }
       double F0[SDC_NH], F1[SDC_NH];
-      hydro_face(WL[0], WR[0], 0, a.gamma, a.alpha, F0, fx[0]);
-      hydro_face(WL[1], WR[1], 0, a.gamma, a.alpha, F1, fx[1]);
+      hydro_face(WLy0, WRy0, 1, a.gamma, a.alpha, F0, fy0);
+      hydro_face(WLy1, WRy1, 1, a.gamma, a.alpha, F1, fy1);
 #pragma unroll
-      for (int q = 0; q < SDC_NH; ++q) acc[q] = -(F1[q] - F0[q]) * idx;
-#pragma unroll
-      for (int q = 0; q < SDC_NH; ++q) {
-        const double v0 = tile[q][ty][tx + 2], v1 = tile[q][ty + 1][tx + 2], v2 = tile[q][ty + 2][tx + 2];
-        const double v3 = tile[q][ty + 3][tx + 2], v4 = tile[q][ty + 4][tx + 2];
-        const double sm = slope_of(v0, v1, v2, a.slope);
-        const double s0 = slope_of(v1, v2, v3, a.slope);
-        const double sp = slope_of(v2, v3, v4, a.slope);
-        WL[0][q] = v1 + 0.5 * sm;
-        WR[0][q] = v2 - 0.5 * s0;
-        WL[1][q] = v2 + 0.5 * s0;
-        WR[1][q] = v3 - 0.5 * sp;
-      }
-      hydro_face(WL[0], WR[0], 1, a.gamma, a.alpha, F0, fy[0]);
-      hydro_face(WL[1], WR[1], 1, a.gamma, a.alpha, F1, fy[1]);
-#pragma unroll
-      for (int q = 0; q < SDC_NH; ++q) acc[q] -= (F1[q] - F0[q]) * idy;
-      double dUk1[SDC_NH];
+      for (int q = 0; q < SDC_NH; ++q) Ay[q] = (F1[q] - F0[q]) * idy;
+      hydro_face(WLz, WRz, 2, a.gamma, a.alpha, F1, fz);
 #pragma unroll
       for (int q = 0; q < SDC_NH; ++q) {
-        const double u2 = (U + (i64)q * Z)[p2 + col];
-        dUk1[q] = slope_of(Uk[q], Uk1[q], u2, a.slope);
-        WL[0][q] = Uk[q] + 0.5 * dUk[q];
-        WR[0][q] = Uk1[q] - 0.5 * dUk1[q];
-        Uk[q] = Uk1[q];
-        Uk1[q] = u2;
+        Az[q] = (F1[q] - Fz[q]) * idz;
+        Fz[q] = F1[q];
+        WLz[q] = WLzn[q];
       }
-      hydro_face(WL[0], WR[0], 2, a.gamma, a.alpha, F1, fz);
-#pragma unroll
-      for (int q = 0; q < SDC_NH; ++q) {
-        acc[q] -= (F1[q] - Fm[q]) * idz;
-        Fm[q] = F1[q];
-        dUk[q] = dUk1[q];
-      }
-      if (active && grp == 0)
-#pragma unroll
-        for (int q = 0; q < SDC_NH; ++q) (a.A + (i64)q * Z)[pk + col] = acc[q];
-    }
-#pragma unroll
-    for (int t = SDC_NH; t < SDC_TC; ++t) {
-      const bool ok = valid(t);
-      const int c = ok ? comp(t) : 0;
-      double As;
-      {
-        const double* r = &tile[t][ty + 2][tx];
-        const double sm = slope_of(r[0], r[1], r[2], a.slope);
-        const double s0 = slope_of(r[1], r[2], r[3], a.slope);
-        const double sp = slope_of(r[2], r[3], r[4], a.slope);
-        const double F0 = species_face(r[1] + 0.5 * sm, r[2] - 0.5 * s0, fx[0]);
-        const double F1 = species_face(r[2] + 0.5 * s0, r[3] - 0.5 * sp, fx[1]);
-        As = -(F1 - F0) * idx;
-      }
-      {
-        const double v0 = tile[t][ty][tx + 2], v1 = tile[t][ty + 1][tx + 2], v2 = tile[t][ty + 2][tx + 2];
-        const double v3 = tile[t][ty + 3][tx + 2], v4 = tile[t][ty + 4][tx + 2];
-        const double sm = slope_of(v0, v1, v2, a.slope);
-        const double s0 = slope_of(v1, v2, v3, a.slope);
-        const double sp = slope_of(v2, v3, v4, a.slope);
-        const double F0 = species_face(v1 + 0.5 * sm, v2 - 0.5 * s0, fy[0]);
-        const double F1 = species_face(v2 + 0.5 * s0, v3 - 0.5 * sp, fy[1]);
-        As -= (F1 - F0) * idy;
-      }
-      {
-        const double u2 = (U + (i64)c * Z)[p2 + col];
-        const double d1 = slope_of(Uk[t], Uk1[t], u2, a.slope);
-        const double F1 = species_face(Uk[t] + 0.5 * dUk[t], Uk1[t] - 0.5 * d1, fz);
-        As -= (F1 - Fm[t]) * idz;
-        Fm[t] = F1;
-        Uk[t] = Uk1[t];
-        Uk1[t] = u2;
-        dUk[t] = d1;
-      }
-      if (active && ok) (a.A + (i64)c * Z)[pk + col] = As;
     }
     __syncthreads();
+    double Fx[SDC_NH];
+    {
+      double WLx[SDC_NH], WRx[SDC_NH];
+#pragma unroll
+      for (int q = 0; q < SDC_NH; ++q) {
+        const double xm2 = sh_u[q][lxm2], xm1 = sh_u[q][lxm1], c = sh_u[q][t], xp1 = sh_u[q][lxp1];
+        const double sA = slope_t<SLOPE>(xm2, xm1, c), sB = slope_t<SLOPE>(xm1, c, xp1);
+        WLx[q] = xm1 + 0.5 * sA;
+        WRx[q] = c - 0.5 * sB;
+      }
+      hydro_face(WLx, WRx, 0, a.gamma, a.alpha, Fx, fx);
+    }
+#pragma unroll
+    for (int q = 0; q < SDC_NH; ++q) sh_fh[q][t] = Fx[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SDC_NH; ++q) {
+      double acc = -((sh_fh[q][lxp1] - Fx[q]) * idx);
+      acc -= Ay[q];
+      acc -= Az[q];
+      if (act) st_at(rA, oc, (unsigned)q * Z8, acc);
+    }
+    // ---- species, with the hydro faces' velocities and speeds
+#pragma unroll
+    for (int s = 0; s < SDC_NS; ++s) {
+      const unsigned so = (unsigned)(SDC_NH + s) * Z8;
+      const double c = ld_at(rU, oc, so);
+      sh_s[t] = c;
+      const double ym2 = ld_at(rU, oc + oy[0], so), ym1 = ld_at(rU, oc + oy[1], so);
+      const double yp1 = ld_at(rU, oc + oy[2], so), yp2 = ld_at(rU, oc + oy[3], so);
+      const double z1 = ld_at(rU, oz1, so), z2 = ld_at(rU, oz2, so);
+      const double sm = slope_t<SLOPE>(ym2, ym1, c), s0 = slope_t<SLOPE>(ym1, c, yp1);
+      const double sp = slope_t<SLOPE>(c, yp1, yp2), s1 = slope_t<SLOPE>(c, z1, z2);
+      const double ay = (species_face(c + 0.5 * s0, yp1 - 0.5 * sp, fy1) - species_face(ym1 + 0.5 * sm, c - 0.5 * s0, fy0)) * idy;
+      const double fzn = species_face(WLz[SDC_NH + s], z1 - 0.5 * s1, fz);
+      const double az = (fzn - Fz[SDC_NH + s]) * idz;
+      Fz[SDC_NH + s] = fzn;
+      WLz[SDC_NH + s] = z1 + 0.5 * s1;
+      __syncthreads();
+      const double xm2 = sh_s[lxm2], xm1 = sh_s[lxm1], xp1 = sh_s[lxp1];
+      const double sA = slope_t<SLOPE>(xm2, xm1, c), sB = slope_t<SLOPE>(xm1, c, xp1);
+      const double fxs = species_face(xm1 + 0.5 * sA, c - 0.5 * sB, fx);
+      sh_fs[t] = fxs;
+      __syncthreads();
+      double acc = -((sh_fs[lxp1] - fxs) * idx);
+      acc -= ay;
+      acc -= az;
+      if (act) st_at(rA, oc, (unsigned)(SDC_NH + s) * Z8, acc);
+    }
   }
+}
+extern "C" __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void sdc_advect_rows(AdvArgs a) {
+  advect_rows_body<1>(a);
+}
+extern "C" __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void sdc_advect_rows_c(AdvArgs a) {
+  advect_rows_body<0>(a);
 }
 #endif
 
@@ -529,6 +558,9 @@ __device__ __forceinline__ int newton_fast(double* x, const double* b, double ir
                                            int& st) {
   int it = it0;
   for (; it <= itmax; ++it) {
+    // keep the parameter reads inside the iteration: hoisted out of the loop
+    // they would pin about 2 NR x 4 registers for its whole length
+    asm volatile("" ::: "memory");
     double G[SDC_NX];
     MT M[SDC_NNZ];
     net_residual_matrix<MT>(x, b, irho, dtm, P, gm1, G, M);
@@ -615,7 +647,7 @@ template <class MT>
 __device__ __forceinline__ void reaction_solve_body(const SolveArgs& a) {
   const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = z < a.Z;
-  ParamPtr P = (ParamPtr)a.P;
+  ParamPtr P = stage_params(a.P);
   double x[SDC_NX], b[SDC_NX], rho = 1.0;
   int it = 0, st = 3;
   if (valid) {
@@ -662,7 +694,7 @@ template <class MT>
 __device__ __forceinline__ void reaction_finish_body(const SolveArgs& a) {
   const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = i < (i64)*a.q.count;
-  ParamPtr P = (ParamPtr)a.P;
+  ParamPtr P = stage_params(a.P);
   int nu = 0, fb = 0;
   bool nonfinite = false;
   if (valid) {
@@ -707,6 +739,7 @@ extern "C" __global__ __launch_bounds__(256) void sdc_reaction_finish(SolveArgs 
 // ---- R(U): the reactive source of a full state, on the reacting variables.
 
 extern "C" __global__ __launch_bounds__(256) void sdc_source(SourceArgs a) {
+  ParamPtr P = stage_params(a.P);
   const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   if (z >= a.Z) return;
   const double rho = a.U[z];
@@ -721,7 +754,7 @@ extern "C" __global__ __launch_bounds__(256) void sdc_source(SourceArgs a) {
 #pragma unroll
   for (int s = 0; s < SDC_NS; ++s) x[s] = a.U[(i64)(SDC_NH + s) * a.Z + z];
   x[SDC_NX - 1] = a.U[(i64)(1 + SDC_DIM) * a.Z + z] - ke;
-  net_source(x, 1.0 / rho, (ParamPtr)a.P, a.gm1, R);
+  net_source(x, 1.0 / rho, P, a.gm1, R);
 #pragma unroll
   for (int i = 0; i < SDC_NX; ++i) a.R[(i64)i * a.Z + z] = R[i];
 }
@@ -769,7 +802,7 @@ template <class MT, int KIND>
 __device__ __forceinline__ void transition_body(const TransArgs& a) {
   const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = z < a.Z;
-  ParamPtr P = (ParamPtr)a.P;
+  ParamPtr P = stage_params(a.P);
   const i64 Z = a.Z;
   double rho = 1.0, ke = 0.0, mom[SDC_DIM];
   double b[SDC_NX], x[SDC_NX];
@@ -868,7 +901,7 @@ template <class MT>
 __device__ __forceinline__ void transition_finish_body(const TransArgs& a) {
   const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = i < (i64)*a.q.count;
-  ParamPtr P = (ParamPtr)a.P;
+  ParamPtr P = stage_params(a.P);
   int nu = 0, fb = 0;
   bool nonfinite = false;
   if (valid) {
@@ -1091,7 +1124,7 @@ template <int FIRST>
 __device__ __forceinline__ void transition_adjoint_body(const TransAdjArgs& a) {
   const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = z < a.Z;
-  ParamPtr P = (ParamPtr)a.P;
+  ParamPtr P = stage_params(a.P);
   double gl[SDC_NRA], gE[SDC_NRA];
 #pragma unroll
   for (int r = 0; r < SDC_NRA; ++r) gl[r] = gE[r] = 0.0;
@@ -1187,7 +1220,7 @@ extern "C" __global__ __launch_bounds__(256) void sdc_transition_adjoint(TransAd
 extern "C" __global__ __launch_bounds__(256) void sdc_source_vjp(SourceVjpArgs a) {
   const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = z < a.Z;
-  ParamPtr P = (ParamPtr)a.P;
+  ParamPtr P = stage_params(a.P);
   double gl[SDC_NRA], gE[SDC_NRA];
 #pragma unroll
   for (int r = 0; r < SDC_NRA; ++r) gl[r] = gE[r] = 0.0;

@@ -179,9 +179,10 @@ std::string generate(const Topology& t, const Pattern& p) {
     << "\n#define SDC_NX " << n << "\n#define SDC_NNZ " << p.nnz << "\n\n";
   E << "struct NetParams { double lnA[SDC_NRA]; double b[SDC_NRA]; double E[SDC_NRA]; double Q[SDC_NRA]; "
        "double q[SDC_NS]; };\n";
-  E << "// Rate parameters are read through the constant address space: uniform\n"
-       "// scalar loads that never occupy vector registers.\n";
-  E << "typedef const __attribute__((address_space(4))) NetParams* ParamPtr;\n\n";
+  E << "// Rate parameters are staged once per block in LDS and read from there:\n"
+       "// wave-uniform (broadcast) LDS reads, so the unrolled Newton loop keeps no\n"
+       "// copy of them in scalar registers (which would spill into vector lanes).\n";
+  E << "typedef const __attribute__((address_space(3))) NetParams* ParamPtr;\n\n";
 
   // common prologue: temperature and its functions
   const char* prologue =

@@ -374,7 +374,7 @@ struct sdc_handle_s {
   int occ2 = 0;
   int cap = 0;  // 0: no cap (newton_maxiter)
   bool tuned = false;
-  hipFunction_t f_advect = nullptr, f_advect3d = nullptr, f_source = nullptr, f_solve = nullptr, f_first = nullptr,
+  hipFunction_t f_advect = nullptr, f_advect_rows = nullptr, f_source = nullptr, f_solve = nullptr, f_first = nullptr,
                 f_node0 = nullptr, f_later = nullptr, f_fill = nullptr;
   void* d_params = nullptr;
   unsigned long long* d_stats = nullptr;
@@ -416,7 +416,7 @@ int fail(sdc_handle h, int code, const std::string& msg) {
   } while (0)
 
 int kind_of(const sdc_handle h, hipFunction_t f) {
-  if (f == h->f_advect || f == h->f_advect3d) return SDC_K_ADVECT;
+  if (f == h->f_advect || f == h->f_advect_rows) return SDC_K_ADVECT;
   if (f == h->f_source) return SDC_K_SOURCE;
   if (f == h->f_solve) return SDC_K_SOLVE;
   if (f == h->f_solve_o2) return SDC_K_SOLVE;
@@ -440,9 +440,15 @@ hipEvent_t take_event(sdc_handle h) {
   return e;
 }
 
+int launch_blocks(sdc_handle h, hipFunction_t f, int64_t nb, void* args, hipStream_t s);
+
 int launch(sdc_handle h, hipFunction_t f, int64_t nthreads, void* args, hipStream_t s) {
   if (nthreads <= 0) return SDC_OK;
-  const int64_t nb = (nthreads + kBlock - 1) / kBlock;
+  return launch_blocks(h, f, (nthreads + kBlock - 1) / kBlock, args, s);
+}
+
+int launch_blocks(sdc_handle h, hipFunction_t f, int64_t nb, void* args, hipStream_t s) {
+  if (nb <= 0) return SDC_OK;
   void* params[] = {args};
   hipEvent_t ea = nullptr, eb = nullptr;
   if (h->profile) {
@@ -527,11 +533,17 @@ int advect(sdc_handle h, const double* U, double* A, hipStream_t s) {
     a.blk_box = h->d_blk_box;
     return launch(h, h->f_advect, h->P.Z, &a, s);
   }
-  if (c.dim == 3 && h->f_advect3d) {
-    // z-marching kernel: one 256-thread block per 64 x 4 column tile and z chunk
-    const int spg = h->ns < 5 ? h->ns : 5, ngrp = (h->ns + spg - 1) / spg;
-    const int64_t nb = ((c.n[0] + 63) / 64) * ((c.n[1] + 3) / 4) * ((c.n[2] + 31) / 32) * ngrp;
-    return launch(h, h->f_advect3d, nb * kBlock, &a, s);
+  if (h->f_advect_rows) {
+    // complete x-rows per block, each marching up a chunk of z planes; the
+    // chunk shrinks until the grid has at least 2048 blocks (or 4 planes)
+    const int64_t n0 = c.n[0], n1 = c.n[1], n2 = c.n[2];
+    const int64_t R = kBlock / n0;
+    int64_t zc = n2 < 32 ? n2 : 32;
+    auto blocks = [&](int64_t z) { return (n1 * ((n2 + z - 1) / z) + R - 1) / R; };
+    while (zc > 4 && blocks(zc) < 2048) zc /= 2;
+    a.rows = (int)R;
+    a.zchunk = (int)zc;
+    return launch_blocks(h, h->f_advect_rows, blocks(zc), &a, s);
   }
   return launch(h, h->f_advect, h->P.Z, &a, s);
 }
@@ -973,12 +985,16 @@ int sdc_init(const sdc_config* cfg, const sdc_network* net, sdc_handle* out) {
     e = hipModuleGetFunction(fn.f, h->mod, fn.name);
     if (e != hipSuccess) return bail(SDC_ERR_HIP, std::string("missing kernel ") + fn.name);
   }
-  // SDC_ADVECT3D=1 selects the z-marching 3D kernel (needs 32-bit offsets
-  // inside one component array); the zone-per-thread kernel is the default
-  const char* ev = std::getenv("SDC_ADVECT3D");
-  if (h->P.cfg.dim == 3 && h->P.cfg.nbox == 0 && h->P.Z < (int64_t(1) << 28) && ev && ev[0] == '1') {
-    e = hipModuleGetFunction(&h->f_advect3d, h->mod, "sdc_advect3d");
-    if (e != hipSuccess) return bail(SDC_ERR_HIP, "missing kernel sdc_advect3d");
+  // 3D single grids with rows of at most 256 zones and state arrays below
+  // 4 GiB (32-bit buffer offsets) use the row kernel (SDC_ADVECT_ROWS=0: the
+  // zone-per-thread kernel everywhere)
+  const char* ev = std::getenv("SDC_ADVECT_ROWS");
+  const sdc_config& gc = h->P.cfg;
+  if (gc.dim == 3 && gc.nbox == 0 && gc.n[0] <= kBlock && 8 * h->nc * h->P.Z < (int64_t(1) << 32) &&
+      !(ev && ev[0] == '0')) {
+    const char* name = gc.slope == 0 ? "sdc_advect_rows_c" : "sdc_advect_rows";
+    e = hipModuleGetFunction(&h->f_advect_rows, h->mod, name);
+    if (e != hipSuccess) return bail(SDC_ERR_HIP, std::string("missing kernel ") + name);
   }
   const std::vector<double> img = params_image(h->P, h->nra);
   e = hipMalloc(&h->d_params, img.size() * sizeof(double));
