@@ -545,52 +545,102 @@ __device__ __attribute__((noinline)) DenseResult dense_newton(VecX xv, VecX bv, 
   return out;
 }
 
+// One zone's vector in a block-shared [SDC_NX][256] LDS array.
+struct LdsVec {
+  __attribute__((address_space(3))) double* p;  // &array[0][threadIdx.x]
+  __device__ double get(int i) const { return p[i * 256]; }
+  __device__ void set(int i, double v) const { p[i * 256] = v; }
+};
+
 // Fast Newton pass for x - dt_m R(x; rho) = b from the iterate in x, running
 // iterations it0..itmax.  Stops when max_i |delta_i| / s_i <= tol (s = rho for
 // species, |b_e| for energy).  Returns the last iteration index and a status:
 // 0 converged, 1 no convergence by itmax, 2 the pivot guard stopped iteration
 // `it` before it changed x, 3 non-finite step.  MT is the type of the Newton
 // matrix and its LU factors (double, or float in the mixed mode where the
-// residual and the update stay in double).  No calls: everything in registers.
+// residual and the update stay in double).  No calls.  b is read back
+// unchanged from LDS at the end.
 template <class MT>
-__device__ __forceinline__ int newton_fast(double* x, const double* b, double irho, double ise, double dtm,
+__device__ __forceinline__ int newton_fast(double* x, double* b, double irho, double ise, double dtm,
                                            ParamPtr P, double gm1, double tol, double tau, int it0, int itmax,
                                            int& st) {
+  // x and b wait in LDS while the Newton matrix and its factors hold the
+  // registers; each iteration reads them back where it needs them
+  __shared__ double sh_x[SDC_NX][256], sh_b[SDC_NX][256];
+  const LdsVec xs{(__attribute__((address_space(3))) double*)&sh_x[0][threadIdx.x]};
+  const LdsVec bs{(__attribute__((address_space(3))) double*)&sh_b[0][threadIdx.x]};
+#ifndef SDC_MIXED
+  __shared__ double sh_g[SDC_NX][256];
+  const LdsVec gs{(__attribute__((address_space(3))) double*)&sh_g[0][threadIdx.x]};
+#else
+  const LdsVec gs{nullptr};
+#endif
+#pragma unroll
+  for (int i = 0; i < SDC_NX; ++i) {
+    xs.set(i, x[i]);
+    bs.set(i, b[i]);
+  }
   int it = it0;
+  st = 1;
   for (; it <= itmax; ++it) {
-    // keep the parameter reads inside the iteration: hoisted out of the loop
-    // they would pin about 2 NR x 4 registers for its whole length
+    // keep the parameter and x/b reads inside the iteration: hoisted out of
+    // the loop they would pin registers for its whole length
     asm volatile("" ::: "memory");
     double G[SDC_NX];
     MT M[SDC_NNZ];
-    net_residual_matrix<MT>(x, b, irho, dtm, P, gm1, G, M);
+    {
+      double xv[SDC_NX], bv[SDC_NX];
+#pragma unroll
+      for (int i = 0; i < SDC_NX; ++i) {
+        xv[i] = xs.get(i);
+        bv[i] = bs.get(i);
+      }
+      net_residual_matrix<MT>(xv, bv, irho, dtm, P, gm1, G, M);
+    }
+    if constexpr (sizeof(MT) == sizeof(double)) {
+      // an FP64 matrix leaves no room for the residual during the factorisation
+#pragma unroll
+      for (int i = 0; i < SDC_NX; ++i) gs.set(i, G[i]);
+      asm volatile("" ::: "memory");
+    }
     if (!net_lu<MT>(M, (MT)tau)) {
       st = 2;
-      return it;
+      break;
+    }
+    if constexpr (sizeof(MT) == sizeof(double)) {
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int i = 0; i < SDC_NX; ++i) G[i] = gs.get(i);
     }
     MT r[SDC_NX];
 #pragma unroll
     for (int i = 0; i < SDC_NX; ++i) r[i] = (MT)(-G[i]);
     net_solve<MT>(M, r);
+    asm volatile("" ::: "memory");
     double err = 0.0, inf_or_nan = ise * 0.0;  // fmax drops NaN, so track it apart
 #pragma unroll
     for (int i = 0; i < SDC_NX; ++i) {
       const double d = (double)r[i];
-      x[i] += d;
+      xs.set(i, xs.get(i) + d);
       err = fmax(err, fabs(d) * (i == SDC_NX - 1 ? ise : irho));
       inf_or_nan += d * 0.0;
     }
     if (!(inf_or_nan == 0.0)) {
       st = 3;
-      return it;
+      break;
     }
     if (err <= tol) {
       st = 0;
-      return it;
+      break;
     }
   }
-  st = 1;
-  return itmax;
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int i = 0; i < SDC_NX; ++i) {
+    x[i] = xs.get(i);
+    b[i] = bs.get(i);
+  }
+  return it > itmax ? itmax : it;
 }
 
 // Queue slot for lanes that defer their zone: one atomic per wavefront.
@@ -609,7 +659,7 @@ __device__ __forceinline__ long long defer_slot(unsigned* count, bool want) {
 // Finish a deferred solve: the fast pass from iteration it0 + 1 (it0 > 0) or
 // the dense pivoted Newton from iteration -it0 (it0 < 0, guard failure).
 template <class MT>
-__device__ __forceinline__ int newton_finish(double* x, const double* b, double rho, double dtm, ParamPtr P, double gm1,
+__device__ __forceinline__ int newton_finish(double* x, double* b, double rho, double dtm, ParamPtr P, double gm1,
                                              const NewtonCtl& ctl, int it0, int& fallbacks) {
   const double irho = 1.0 / rho;
   const double ise = 1.0 / fabs(b[SDC_NX - 1]);

@@ -101,10 +101,10 @@ std::string accum(const std::string& acc, double s, const std::string& val) {
 }
 
 std::string accum_t(const std::string& acc, double s, const std::string& val) {
-  // matrix accumulation in the matrix type MT
-  if (s == 1.0) return acc + " += (MT)(" + val + ");";
-  if (s == -1.0) return acc + " -= (MT)(" + val + ");";
-  return acc + " += (MT)(" + num(s) + " * " + val + ");";
+  // matrix accumulation in the matrix type MT; val is already of type MT
+  if (s == 1.0) return acc + " += " + val + ";";
+  if (s == -1.0) return acc + " -= " + val + ";";
+  return acc + " = fma((MT)" + num(s) + ", " + val + ", " + acc + ");";
 }
 
 void emit_rate(Emit& E, int r, const Rx& x) {
@@ -183,6 +183,14 @@ std::string generate(const Topology& t, const Pattern& p) {
        "// wave-uniform (broadcast) LDS reads, so the unrolled Newton loop keeps no\n"
        "// copy of them in scalar registers (which would spill into vector lanes).\n";
   E << "typedef const __attribute__((address_space(3))) NetParams* ParamPtr;\n\n";
+  E << "// Reciprocal from the hardware estimate: two Newton steps in double (within\n"
+       "// an ulp of 1/d, about half the cost of an IEEE division); the float\n"
+       "// estimate alone is within an ulp.\n";
+  E << "__device__ __forceinline__ double net_rcp(double d) {\n"
+       "  double r = __builtin_amdgcn_rcp(d);\n"
+       "  double e = fma(-d, r, 1.0);\n  r = fma(r, e, r);\n"
+       "  e = fma(-d, r, 1.0);\n  return fma(r, e, r);\n}\n";
+  E << "__device__ __forceinline__ float net_rcp(float d) { return __builtin_amdgcn_rcpf(d); }\n\n";
 
   // common prologue: temperature and its functions
   const char* prologue =
@@ -240,13 +248,14 @@ std::string generate(const Topology& t, const Pattern& p) {
       auto d = rate_derivs(r, rx[r], e);
       for (size_t q = 0; q < d.size(); ++q) {
         int j = d[q].first;
-        E << "    const double m" << q << " = mdt * (" << d[q].second << ");\n";
+        // one rounding to MT per derivative; the scatter runs in MT
+        E << "    const MT m" << q << " = (MT)(mdt * (" << d[q].second << "));\n";
         for (auto& [i, s] : rx[r].s) {
           std::string slot = dense ? std::to_string(i * n + j) : std::to_string(p.index[i * n + j]);
           E << "    " << accum_t("M[" + slot + "]", s, "m" + std::to_string(q)) << "\n";
         }
         std::string slot = dense ? std::to_string(e * n + j) : std::to_string(p.index[e * n + j]);
-        E << "    M[" << slot << "] += (MT)(P->Q[" << r << "] * m" << q << ");\n";
+        E << "    M[" << slot << "] = fma((MT)P->Q[" << r << "], m" << q << ", M[" << slot << "]);\n";
       }
       E << "  }\n";
     }
@@ -303,7 +312,7 @@ std::string generate(const Topology& t, const Pattern& p) {
     } else {
       E << "    ok = ok && (fabs(piv) >= tau * fabs(piv)) && (piv != (MT)0);\n";
     }
-    E << "    const MT inv = (MT)1 / piv;\n    M[" << dk << "] = inv;\n";
+    E << "    const MT inv = net_rcp(piv);\n    M[" << dk << "] = inv;\n";
     for (int i : rows) {
       int li = p.index[i * n + k];
       E << "    { const MT l = M[" << li << "] * inv; M[" << li << "] = l;\n";
