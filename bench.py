@@ -11,10 +11,13 @@ are resident in HBM before the timed region, which brackets exactly K steps
 with device synchronisation.  Prints one JSON line.
 
 The FP64 path gives `value`; the mixed path (FP32 Newton matrix and LU) is
-reported beside it.  `roofline` covers the dominant kernels (the fused
-transition kernels), timed with HIP events on the launch stream inside the
-timed region.  `cpu_baseline` times the CPU oracle on a bounded sub-volume of
-the same workload (single thread).
+reported beside it.  `roofline` covers the dominant kernel (the fused m = 0
+node transition, sdc_transition_node0), timed with HIP events on the launch
+stream inside the timed region, against the ceiling its algorithmic bytes and
+flops make binding; `traffic` is the HBM bytes per launch from the committed
+counter summary when that was taken on the same kernel source.
+`cpu_baseline` times the CPU oracle on a bounded sub-volume of the same
+workload (single thread).
 """
 from __future__ import annotations
 
@@ -35,55 +38,107 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X vector FP64 (FMA counts 2)
 PEAK_HBM_GBS = 8000.0
 
 
-def transition_model(h, work_kinds, stats, nlaunch):
-    """Algorithmic flops and HBM bytes of the transition launches.
+def kernel_model(h, stats):
+    """Algorithmic FP64 bytes and flops per zone of each kernel launch.
 
-    Flops: every Newton iteration costs the residual/matrix assembly, the LU
-    and the triangular solves of the generated code (plus 2 n_r for the
-    update and test); every solve adds one R(x) evaluation and the explicit
-    update (about 4 n_c).  Bytes: each kernel's reads and writes of state,
-    advective, source and correction arrays, once each, in FP64.
+    Bytes: every state, advective, source and correction array a kernel reads
+    or writes, once each, 8 bytes per value.  Flops: a Newton iteration costs
+    the residual/matrix assembly, the LU and the triangular solves of the
+    generated network code (exp and log count one each) plus 2 n_x for the
+    update and the test; a solve adds one R(x) at the root and the explicit
+    update (about 4 n_c); the quadrature of the m = 0 transition adds
+    2 (M+1)(n_c + n_x) per correction term.  The Newton count is the measured
+    mean over the timed steps.
     """
     cm = h.cost_model()
     nx, nc, M = h.nreact_vars, h.ncomp, h.n_nodes - 1
     per_iter = cm["residual_matrix"] + cm["lu"] + cm["solve"] + 2 * nx
     per_solve = cm["source"] + 4 * nc
-    flops = stats["iters"] * per_iter + stats["solves"] * per_solve
-    Z = h.zones
+    nu = stats["iters"] / max(stats["solves"] - stats["failed"], 1)
+    newton = nu * per_iter + per_solve
     words = {
         "transition_first": 3 * nc + (nc + nx),
         "transition_node0": (M + 1) * (nc + nx) + 2 * nc + (nc + nx) + (M - 1) * nc,
         "transition_later": 4 * nc + (nc + nx),
+        "advect": 2 * nc,
+        "source": nc + nx,
     }
-    bytes_ = sum(8.0 * Z * words[k] * nlaunch[k] for k in work_kinds)
-    return flops, bytes_, per_iter, per_solve
+    flops = {
+        "transition_first": newton + 2 * nc,
+        "transition_node0": newton + 2 * (M + 1) * (nc + nx) * M,
+        "transition_later": newton + 3 * nc,
+    }
+    return {k: 8.0 * v for k, v in words.items()}, flops, per_iter, per_solve
 
 
-def set_schedule(h, schedule, dt, U, work):
-    """'auto': time every Newton schedule on the initial state (untimed
-    set-up, like a GEMM heuristic); 'O,C': fixed occupancy variant and cap."""
-    t0 = time.perf_counter()
-    if schedule == "auto":
-        occ2, cap = h.autotune(dt, U, work)
-    else:
+def roofline(bytes_per_zone, flops_per_zone, zones, avg_s):
+    """Roofline of one kernel from its algorithmic bytes and flops per launch
+    and its measured mean launch time: the binding ceiling is the larger of
+    bytes / HBM peak and flops / FP64 peak."""
+    B, F = bytes_per_zone * zones, flops_per_zone * zones
+    t_hbm, t_alu = B / (PEAK_HBM_GBS * 1e9), F / (PEAK_FP64_TFLOPS * 1e12)
+    hbm = dict(achieved=B / avg_s / 1e9, peak=PEAK_HBM_GBS, unit="GB/s", frac=t_hbm / avg_s)
+    alu = dict(achieved=F / avg_s / 1e12, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s", frac=t_alu / avg_s)
+    bound = "hbm" if t_hbm >= t_alu else "alu"
+    main = hbm if bound == "hbm" else alu
+    return dict(bound=bound, **main, bytes_per_launch=B, flops_per_launch=F, avg_launch_ms=1e3 * avg_s,
+                hbm_frac=hbm["frac"], alu_frac=alu["frac"], alu_TFLOPs=alu["achieved"], hbm_GBs=hbm["achieved"])
+
+
+def recorded_traffic(h, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    if it was taken on the kernel source this handle compiled (else None)."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{kernel}_net3d_256cubed.md")
+    if not os.path.exists(path):
+        return None, None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                rec[k.strip()] = v.strip().strip("`")
+    import hashlib
+    src = h.generated_source()
+    digest = hashlib.sha256(src.encode()).hexdigest()[:16]
+    if rec.get("source_sha256_16") != digest or "traffic_bytes_per_launch" not in rec:
+        return None, digest
+    return float(rec["traffic_bytes_per_launch"]), digest
+
+
+def make_handle(w, precision, schedule):
+    """'auto': the handle tunes its Newton schedule on its first step (or reads
+    the choice cached on disk for this kernel source and size); 'O,C': fixed
+    occupancy variant and iteration cap."""
+    from paper_1910_12578_amd import SDC, config_from_workload
+    h = SDC(config_from_workload(w, precision=precision, autotune=int(schedule == "auto")), w["network"])
+    if schedule != "auto":
         occ2, cap = (int(v) for v in schedule.split(","))
         h.set_schedule(occ2, cap)
-    return dict(occ2=occ2, cap=cap, mode=schedule, setup_s=round(time.perf_counter() - t0, 3))
+    return h
+
+
+def warm(h, dt, U, work, warmup, schedule):
+    """Untimed warmup steps; the first one includes the schedule tuning."""
+    import torch
+    t0 = time.perf_counter()
+    if warmup > 0:
+        h.step(dt, warmup, U, work)
+    elif schedule == "auto":
+        h.autotune(dt, U, work)
+    torch.cuda.synchronize()
+    occ2, cap = h.schedule()
+    return dict(occ2=occ2, cap=cap, mode=schedule, warmup_s=round(time.perf_counter() - t0, 3))
 
 
 def run_gpu(w, precision, steps, warmup, schedule="auto"):
     import torch
-    from paper_1910_12578_amd import SDC, config_from_workload
-    cfg = config_from_workload(w, precision=precision)
-    h = SDC(cfg, w["network"])
+    h = make_handle(w, precision, schedule)
     nc = w["U0"].shape[0]
     U = torch.from_numpy(w["U0"].reshape(nc, -1)).to("cuda")
     work = h.alloc_nodes()
     dt = w["dt"]
     stream = torch.cuda.current_stream()
-    sched = set_schedule(h, schedule, dt, U, work)
-    h.step(dt, warmup, U, work)
-    torch.cuda.synchronize()
+    sched = warm(h, dt, U, work, warmup, schedule)
     h.stats_reset()
     h.profile(True)
     torch.cuda.synchronize()
@@ -95,20 +150,25 @@ def run_gpu(w, precision, steps, warmup, schedule="auto"):
     h.profile(False)
     st = h.stats()
     ok = bool(torch.isfinite(U).all().item())
-    kinds = ("transition_first", "transition_node0", "transition_later")
-    nlaunch = {k: prof[k][1] for k in kinds}
-    # one transition = its fast-pass kernel plus the finish kernel of the
-    # zones it deferred; both carry the Newton work the flop model counts
-    t_trans = (sum(prof[k][0] for k in kinds) + prof["finish"][0]) * 1e-3
-    flops, bytes_, per_iter, per_solve = transition_model(h, kinds, st, nlaunch)
+    Z = w["U0"][0].size
+    bpz, fpz, per_iter, per_solve = kernel_model(h, st)
+    # the dominant kernel: the m = 0 transition (quadrature of every node,
+    # correction terms, explicit update, Newton), timed with HIP events
+    dom = "transition_node0"
+    avg = prof[dom][0] * 1e-3 / max(prof[dom][1], 1)
+    roof = roofline(bpz[dom], fpz[dom], Z, avg)
+    traffic, digest = recorded_traffic(h, "sdc_" + dom)
+    roof["traffic"] = traffic
+    roof["kernel"] = "sdc_" + dom
+    # whole step against the HBM roofline: every launch's algorithmic bytes
+    step_bytes = sum(bpz[k] * Z * prof[k][1] for k in bpz if prof[k][1])
     res = dict(
-        elapsed=elapsed, ms_per_step=1e3 * elapsed / steps, zone_updates=w["U0"][0].size * steps / elapsed,
+        elapsed=elapsed, ms_per_step=1e3 * elapsed / steps, zone_updates=Z * steps / elapsed,
         stats=st, mean_newton=st["iters"] / max(st["solves"] - st["failed"], 1), finite=ok,
         profile={k: dict(ms=round(v[0], 3), launches=v[1]) for k, v in prof.items() if v[1]},
-        transition=dict(seconds=t_trans, flops=flops, bytes=bytes_, flops_per_iter=per_iter,
-                        flops_per_solve=per_solve,
-                        avg_launch_ms=1e3 * t_trans / max(sum(nlaunch.values()), 1)),
-        cost_model=h.cost_model(), schedule=sched,
+        roofline=roof, step_hbm_frac=step_bytes / elapsed / (PEAK_HBM_GBS * 1e9),
+        flops_per_newton_iteration=per_iter, flops_per_solve=per_solve,
+        cost_model=h.cost_model(), schedule=sched, source_sha256_16=digest,
     )
     h.close()
     del U, work
@@ -165,15 +225,11 @@ def run_adjoint_ratio(nsteps=20):
 def run_boxes(steps, warmup, precision, schedule="auto"):
     """Batched boxes: 4096 periodic boxes, edges in {8,16,32,64}, one launch per kernel."""
     import torch
-    from paper_1910_12578_amd import SDC, config_from_workload
     w = si.boxes_workload()
-    h = SDC(config_from_workload(w, precision=precision), w["network"])
-    nc = w["U0"].shape[0]
+    h = make_handle(w, precision, schedule)
     U = torch.from_numpy(w["U0"]).to("cuda")
     work = h.alloc_nodes()
-    sched = set_schedule(h, schedule, w["dt"], U, work)
-    h.step(w["dt"], warmup, U, work)
-    torch.cuda.synchronize()
+    sched = warm(h, w["dt"], U, work, warmup, schedule)
     h.stats_reset()
     t0 = time.perf_counter()
     h.step(w["dt"], steps, U, work)
@@ -218,12 +274,12 @@ def main():
     ap.add_argument("--workload", default="net3d")
     ap.add_argument("--shape", default=None, help="override grid, e.g. 64,64,64")
     ap.add_argument("--precision", default="both", choices=("fp64", "mixed", "both"))
-    ap.add_argument("--cpu-edge", type=int, default=32)
+    ap.add_argument("--cpu-edge", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward time ratio")
     ap.add_argument("--boxes", action="store_true", help="also time the 4096-box batched workload")
     ap.add_argument("--schedule", default="auto",
-                    help="Newton kernel schedule: 'auto' (autotune before warmup) or 'OCC2,CAP', e.g. 0,0")
+                    help="Newton kernel schedule: 'auto' (tuned on the first warmup step) or 'OCC2,CAP', e.g. 0,0")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (calibrates HBM byte counters)")
     a = ap.parse_args()
@@ -242,8 +298,7 @@ def main():
             runs[name] = run_gpu(w, prec, a.steps, a.warmup, a.schedule)
             print(f"[bench] {name}: {runs[name]['zone_updates']:.4e} zone-updates/s", file=sys.stderr, flush=True)
     head = runs.get("fp64") or runs["mixed"]
-    tr = head["transition"]
-    achieved = tr["flops"] / tr["seconds"] / 1e12 if tr["seconds"] > 0 else 0.0
+    roof = dict(head["roofline"])
     out = dict(
         metric="SDC zone-updates/s, 256^3 x 13 species, FP64 (mixed and adjoint/forward time beside it)",
         value=head["zone_updates"],
@@ -256,22 +311,22 @@ def main():
         config=dict(workload=f"{a.workload} {'x'.join(map(str, w['shape']))}, {w['network']['nspec']} species / "
                              f"{w['network']['nreact']} reactions, {w['n_nodes']} Gauss-Lobatto nodes, "
                              f"K={w['n_iters']}", zones=Z, dt=w["dt"]),
-        roofline=dict(bound="alu", kernel="sdc_transition_* + sdc_transition_finish "
-                                          "(fused quadrature + explicit update + Newton)",
-                      achieved=achieved, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                      frac=achieved / PEAK_FP64_TFLOPS, traffic=None,
-                      hbm_achieved_GBs=tr["bytes"] / tr["seconds"] / 1e9 if tr["seconds"] > 0 else 0.0,
-                      avg_launch_ms=tr["avg_launch_ms"]),
+        roofline=roof,
+        step_hbm_frac=head["step_hbm_frac"],
         schedule=head["schedule"],
         mean_newton_iterations=head["mean_newton"],
         newton_failed=head["stats"]["failed"],
+        newton_hist={i: v for i, v in enumerate(head["stats"]["hist"]) if v},
         kernels_ms=head["profile"],
     )
     if "mixed" in runs and "fp64" in runs:
-        out["mixed"] = dict(value=runs["mixed"]["zone_updates"], ms_per_step=runs["mixed"]["ms_per_step"],
-                            speedup_vs_fp64=runs["mixed"]["zone_updates"] / runs["fp64"]["zone_updates"],
-                            mean_newton_iterations=runs["mixed"]["mean_newton"], schedule=runs["mixed"]["schedule"],
-                            kernels_ms=runs["mixed"]["profile"])
+        mx = runs["mixed"]
+        out["mixed"] = dict(value=mx["zone_updates"], ms_per_step=mx["ms_per_step"],
+                            speedup_vs_fp64=mx["zone_updates"] / runs["fp64"]["zone_updates"],
+                            mean_newton_iterations=mx["mean_newton"], schedule=mx["schedule"],
+                            roofline={k: mx["roofline"][k] for k in ("kernel", "bound", "frac", "achieved", "unit",
+                                                                     "avg_launch_ms", "hbm_frac", "alu_frac")},
+                            step_hbm_frac=mx["step_hbm_frac"], kernels_ms=mx["profile"])
     if not a.no_adjoint:
         print("[bench] adjoint/forward ratio", file=sys.stderr, flush=True)
         out["adjoint"] = run_adjoint_ratio()

@@ -298,6 +298,10 @@ class SDC:
                                       self._stream(stream)), self._h)
         return Ubar_n, thetabar
 
+    def generated_source(self):
+        """The device source this handle compiled (generated network code + kernels)."""
+        return generated_source(self.cfg, self.net)
+
     def set_schedule(self, occ2, cap):
         _check(lib().sdc_set_schedule(self._h, int(occ2), int(cap)), self._h)
 

@@ -25,6 +25,16 @@ typedef struct {
   sdc_i64 capacity;
 } DeferQueue;
 
+// Work of one block of the row advection kernel: a run of `slots` (x-row,
+// z-chunk) pairs of one periodic grid (the whole domain, or one box).
+typedef struct {
+  sdc_i64 base;  // zone offset of the grid in the state arrays
+  int n0, n1, n2;
+  int zc;        // planes per z chunk
+  int slot0;     // first slot of the block; slot = y + n1 * chunk
+  int nslot;     // slots of the grid: n1 * ceil(n2 / zc)
+} RowDesc;
+
 typedef struct {
   const double* U;
   double* A;
@@ -40,9 +50,8 @@ typedef struct {
   const sdc_i64* box_off;
   const int* box_ext;
   const int* blk_box;
-  // row kernel (3D): complete x-rows per 256-thread block, z planes per chunk
-  int rows;
-  int zchunk;
+  // row kernel (3D): one descriptor per block
+  const RowDesc* rows;
 } AdvArgs;
 
 typedef struct {

@@ -239,7 +239,9 @@ __device__ __forceinline__ double species_face(double L, double R, const FaceHyd
 
 #if SDC_DIM == 3
 // ---- 3D advective term: complete x-rows per block, marching in z.
-// A 256-thread block holds R = 256 / n0 complete x-rows, periodic in x, so
+// A 256-thread block holds R = 256 / n0 complete x-rows of one periodic grid
+// (the domain, or one of the batched boxes; a per-block descriptor says which
+// rows and z chunk), periodic in x, so
 // every x-face flux is computed once (by the zone to its right) and handed to
 // the zone on its left through LDS.  Each row marches up a chunk of planes in
 // z carrying, per component, the left state of the face above the current
@@ -278,16 +280,16 @@ __device__ __forceinline__ void advect_rows_body(const AdvArgs& a) {
   __shared__ double sh_fh[SDC_NH][256];  // hydro x-face fluxes
   __shared__ double sh_s[256];           // one species component
   __shared__ double sh_fs[256];          // its x-face flux
-  const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
-  const int R = a.rows, ZC = a.zchunk;
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  const RowDesc d = a.rows[b];
+  const int n0 = d.n0, n1 = d.n1, n2 = d.n2, ZC = d.zc;
+  const int R = 256 / n0;
   const int t = threadIdx.x;
   const int r = t / n0, x = t - r * n0;
-  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-  const long long nslot = (long long)n1 * ((n2 + ZC - 1) / ZC);
-  const long long slot = (long long)b * R + r;
-  const bool row_ok = r < R && slot < nslot;
-  const int y = row_ok ? (int)(slot % n1) : 0;
-  const int k0 = row_ok ? (int)(slot / n1) * ZC : 0;
+  const int slot = d.slot0 + r;
+  const bool row_ok = r < R && slot < d.nslot;
+  const int y = row_ok ? slot % n1 : 0;
+  const int k0 = row_ok ? (slot / n1) * ZC : 0;
   const int k1 = row_ok ? min(k0 + ZC, n2) : 0;
   // LDS slots of the x neighbours; idle lanes (r >= R) only touch their own slot
   const int rb = (r < R ? r : 0) * n0, xx = r < R ? x : 0;
@@ -295,7 +297,7 @@ __device__ __forceinline__ void advect_rows_body(const AdvArgs& a) {
   const int lxm1 = r < R ? rb + wrap_index(xx - 1, n0) : t;
   const int lxp1 = r < R ? rb + wrap_index(xx + 1, n0) : t;
   const unsigned P8 = (unsigned)n0 * (unsigned)n1 * 8u;  // plane stride in bytes
-  const unsigned row8 = ((unsigned)y * (unsigned)n0 + (unsigned)xx) * 8u;
+  const unsigned row8 = ((unsigned)d.base + (unsigned)y * (unsigned)n0 + (unsigned)xx) * 8u;
   unsigned oy[4];  // byte offsets of rows y-2, y-1, y+1, y+2 relative to row y
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -303,9 +305,9 @@ __device__ __forceinline__ void advect_rows_body(const AdvArgs& a) {
     oy[j] = (unsigned)((wrap_index(y + dy, n1) - y) * n0) * 8u;
   }
   const i64 Z = a.Z;
-  const __amdgpu_buffer_rsrc_t rU = array_rsrc(a.U, (i64)SDC_NC * Z * 8);
-  const __amdgpu_buffer_rsrc_t rA = array_rsrc(a.A, (i64)SDC_NC * Z * 8);
-  const unsigned Z8 = (unsigned)Z * 8u;  // component stride in bytes
+  // one buffer resource per component array (each below 4 GiB)
+  auto rU = [&](int c) { return array_rsrc(a.U + (i64)c * Z, Z * 8); };
+  auto rA = [&](int c) { return array_rsrc(a.A + (i64)c * Z, Z * 8); };
   const double idx = a.idx[0], idy = a.idx[1], idz = a.idx[2];
 
   // prologue: the face below plane k0 and the left state of the face above it
@@ -316,8 +318,8 @@ __device__ __forceinline__ void advect_rows_body(const AdvArgs& a) {
     double WL[SDC_NH], WR[SDC_NH];
 #pragma unroll
     for (int q = 0; q < SDC_NH; ++q) {
-      const unsigned so = (unsigned)q * Z8;
-      const double v0 = ld_at(rU, o0, so), v1 = ld_at(rU, o1, so), v2 = ld_at(rU, o2, so), v3 = ld_at(rU, o3, so);
+      const __amdgpu_buffer_rsrc_t rq = rU(q);
+      const double v0 = ld_at(rq, o0, 0), v1 = ld_at(rq, o1, 0), v2 = ld_at(rq, o2, 0), v3 = ld_at(rq, o3, 0);
       const double sA = slope_t<SLOPE>(v0, v1, v2), sB = slope_t<SLOPE>(v1, v2, v3);
       WL[q] = v1 + 0.5 * sA;
       WR[q] = v2 - 0.5 * sB;
@@ -327,8 +329,8 @@ __device__ __forceinline__ void advect_rows_body(const AdvArgs& a) {
     hydro_face(WL, WR, 2, a.gamma, a.alpha, Fz, fzm);
 #pragma unroll
     for (int s = 0; s < SDC_NS; ++s) {
-      const unsigned so = (unsigned)(SDC_NH + s) * Z8;
-      const double v0 = ld_at(rU, o0, so), v1 = ld_at(rU, o1, so), v2 = ld_at(rU, o2, so), v3 = ld_at(rU, o3, so);
+      const __amdgpu_buffer_rsrc_t rq = rU(SDC_NH + s);
+      const double v0 = ld_at(rq, o0, 0), v1 = ld_at(rq, o1, 0), v2 = ld_at(rq, o2, 0), v3 = ld_at(rq, o3, 0);
       const double sA = slope_t<SLOPE>(v0, v1, v2), sB = slope_t<SLOPE>(v1, v2, v3);
       Fz[SDC_NH + s] = species_face(v1 + 0.5 * sA, v2 - 0.5 * sB, fzm);
       WLz[SDC_NH + s] = v2 + 0.5 * sB;
@@ -349,12 +351,12 @@ __device__ __forceinline__ void advect_rows_body(const AdvArgs& a) {
       double WLy0[SDC_NH], WRy0[SDC_NH], WLy1[SDC_NH], WRy1[SDC_NH], WRz[SDC_NH], WLzn[SDC_NH];
 #pragma unroll
       for (int q = 0; q < SDC_NH; ++q) {
-        const unsigned so = (unsigned)q * Z8;
-        const double c = ld_at(rU, oc, so);
+        const __amdgpu_buffer_rsrc_t rq = rU(q);
+        const double c = ld_at(rq, oc, 0);
         sh_u[q][t] = c;
-        const double ym2 = ld_at(rU, oc + oy[0], so), ym1 = ld_at(rU, oc + oy[1], so);
-        const double yp1 = ld_at(rU, oc + oy[2], so), yp2 = ld_at(rU, oc + oy[3], so);
-        const double z1 = ld_at(rU, oz1, so), z2 = ld_at(rU, oz2, so);
+        const double ym2 = ld_at(rq, oc + oy[0], 0), ym1 = ld_at(rq, oc + oy[1], 0);
+        const double yp1 = ld_at(rq, oc + oy[2], 0), yp2 = ld_at(rq, oc + oy[3], 0);
+        const double z1 = ld_at(rq, oz1, 0), z2 = ld_at(rq, oz2, 0);
         const double sm = slope_t<SLOPE>(ym2, ym1, c), s0 = slope_t<SLOPE>(ym1, c, yp1);
         const double sp = slope_t<SLOPE>(c, yp1, yp2), s1 = slope_t<SLOPE>(c, z1, z2);
         WLy0[q] = ym1 + 0.5 * sm;
@@ -398,17 +400,17 @@ __device__ __forceinline__ void advect_rows_body(const AdvArgs& a) {
       double acc = -((sh_fh[q][lxp1] - Fx[q]) * idx);
       acc -= Ay[q];
       acc -= Az[q];
-      if (act) st_at(rA, oc, (unsigned)q * Z8, acc);
+      if (act) st_at(rA(q), oc, 0, acc);
     }
     // ---- species, with the hydro faces' velocities and speeds
 #pragma unroll
     for (int s = 0; s < SDC_NS; ++s) {
-      const unsigned so = (unsigned)(SDC_NH + s) * Z8;
-      const double c = ld_at(rU, oc, so);
+      const __amdgpu_buffer_rsrc_t rq = rU(SDC_NH + s);
+      const double c = ld_at(rq, oc, 0);
       sh_s[t] = c;
-      const double ym2 = ld_at(rU, oc + oy[0], so), ym1 = ld_at(rU, oc + oy[1], so);
-      const double yp1 = ld_at(rU, oc + oy[2], so), yp2 = ld_at(rU, oc + oy[3], so);
-      const double z1 = ld_at(rU, oz1, so), z2 = ld_at(rU, oz2, so);
+      const double ym2 = ld_at(rq, oc + oy[0], 0), ym1 = ld_at(rq, oc + oy[1], 0);
+      const double yp1 = ld_at(rq, oc + oy[2], 0), yp2 = ld_at(rq, oc + oy[3], 0);
+      const double z1 = ld_at(rq, oz1, 0), z2 = ld_at(rq, oz2, 0);
       const double sm = slope_t<SLOPE>(ym2, ym1, c), s0 = slope_t<SLOPE>(ym1, c, yp1);
       const double sp = slope_t<SLOPE>(c, yp1, yp2), s1 = slope_t<SLOPE>(c, z1, z2);
       const double ay = (species_face(c + 0.5 * s0, yp1 - 0.5 * sp, fy1) - species_face(ym1 + 0.5 * sm, c - 0.5 * s0, fy0)) * idy;
@@ -425,7 +427,7 @@ __device__ __forceinline__ void advect_rows_body(const AdvArgs& a) {
       double acc = -((sh_fs[lxp1] - fxs) * idx);
       acc -= ay;
       acc -= az;
-      if (act) st_at(rA, oc, (unsigned)(SDC_NH + s) * Z8, acc);
+      if (act) st_at(rA(SDC_NH + s), oc, 0, acc);
     }
   }
 }
@@ -550,6 +552,7 @@ struct LdsVec {
   __attribute__((address_space(3))) double* p;  // &array[0][threadIdx.x]
   __device__ double get(int i) const { return p[i * 256]; }
   __device__ void set(int i, double v) const { p[i * 256] = v; }
+  __device__ double operator[](int i) const { return p[i * 256]; }
 };
 
 // Fast Newton pass for x - dt_m R(x; rho) = b from the iterate in x, running
@@ -588,15 +591,7 @@ __device__ __forceinline__ int newton_fast(double* x, double* b, double irho, do
     asm volatile("" ::: "memory");
     double G[SDC_NX];
     MT M[SDC_NNZ];
-    {
-      double xv[SDC_NX], bv[SDC_NX];
-#pragma unroll
-      for (int i = 0; i < SDC_NX; ++i) {
-        xv[i] = xs.get(i);
-        bv[i] = bs.get(i);
-      }
-      net_residual_matrix<MT>(xv, bv, irho, dtm, P, gm1, G, M);
-    }
+    net_residual_matrix<MT>(xs, bs, irho, dtm, P, gm1, G, M);
     if constexpr (sizeof(MT) == sizeof(double)) {
       // an FP64 matrix leaves no room for the residual during the factorisation
 #pragma unroll
@@ -1206,7 +1201,7 @@ __device__ __forceinline__ void transition_adjoint_body(const TransAdjArgs& a) {
     // implicit solve: mu = M^{-T} xbar at the converged root
     {
       double G[SDC_NX], Mtx[SDC_NNZ];
-      net_residual_matrix<double>(x, x, irho, a.dtm, P, a.gm1, G, Mtx);
+      net_residual_matrix<double, const double*>(x, x, irho, a.dtm, P, a.gm1, G, Mtx);
       if (net_lu<double>(Mtx, a.tau)) {
         net_solve_t<double>(Mtx, mu);
       } else {

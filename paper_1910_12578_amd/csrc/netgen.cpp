@@ -217,7 +217,9 @@ std::string generate(const Topology& t, const Pattern& p) {
   auto emit_residual_matrix = [&](bool dense) {
     if (!dense) {
       E << "// G = x - b - dt_m R(x) and the packed Newton matrix M = I - dt_m dR/dx.\n";
-      E << "template <class MT>\n__device__ __forceinline__ void net_residual_matrix(const double* x, const double* b, "
+      E << "// XV: any type with double operator[](int) (a register array, or the\n"
+           "// zone's slots of an LDS array that are read where they are needed).\n";
+      E << "template <class MT, class XV>\n__device__ __forceinline__ void net_residual_matrix(const XV& x, const XV& b, "
            "double irho, double dtm, ParamPtr P, double gm1, double* G, MT* M) {\n";
     } else {
       E << "// Same as net_residual_matrix, into a dense row-major n x n array (pivoting fallback).\n";

@@ -381,6 +381,8 @@ struct sdc_handle_s {
   int64_t* d_box_off = nullptr;
   int32_t* d_box_ext = nullptr;
   int32_t* d_blk_box = nullptr;
+  RowDesc* d_rows = nullptr;  // row advection kernel: one descriptor per block
+  int64_t n_rows = 0;
   hipStream_t last_stream = nullptr;
   std::string err;
   // per-kernel timing
@@ -511,6 +513,55 @@ int reset_queue(sdc_handle h, hipStream_t s) {
   return SDC_OK;
 }
 
+// Blocks of the row advection kernel: every periodic grid (the domain, or
+// each box) is cut into slots (x-row y, z chunk), R = 256 / n0 slots per
+// block.  The chunk length is halved until the grid fills its blocks (boxes)
+// or the domain gives at least 2048 blocks, down to 2 (4) planes.
+std::vector<RowDesc> row_descriptors(const Prepared& P) {
+  std::vector<RowDesc> out;
+  auto add_grid = [&](int64_t base, int n0, int n1, int n2, bool domain) {
+    const int R = kBlock / n0;
+    int zc = n2 < 32 ? n2 : 32;
+    auto slots = [&](int z) { return (int64_t)n1 * ((n2 + z - 1) / z); };
+    if (domain)
+      while (zc > 4 && (slots(zc) + R - 1) / R < 2048) zc = (zc + 1) / 2;
+    else
+      while (zc > 2 && slots(zc) < R) zc = (zc + 1) / 2;
+    const int64_t ns = slots(zc);
+    for (int64_t s0 = 0; s0 < ns; s0 += R) {
+      RowDesc d;
+      d.base = base;
+      d.n0 = n0;
+      d.n1 = n1;
+      d.n2 = n2;
+      d.zc = zc;
+      d.slot0 = (int)s0;
+      d.nslot = (int)ns;
+      out.push_back(d);
+    }
+  };
+  const sdc_config& c = P.cfg;
+  if (c.nbox > 0)
+    for (int b = 0; b < c.nbox; ++b)
+      add_grid(P.box_off[b], P.box_ext[3 * b], P.box_ext[3 * b + 1], P.box_ext[3 * b + 2], false);
+  else
+    add_grid(0, (int)c.n[0], (int)c.n[1], (int)c.n[2], true);
+  return out;
+}
+
+// The row kernel takes 3D grids whose x-rows fit one block and whose
+// component arrays stay below 4 GiB (32-bit buffer offsets).
+bool rows_kernel_fits(const Prepared& P) {
+  const sdc_config& c = P.cfg;
+  if (c.dim != 3 || 8 * P.Z >= (int64_t(1) << 32)) return false;
+  if (c.nbox > 0) {
+    for (int b = 0; b < c.nbox; ++b)
+      if (P.box_ext[3 * b] > kBlock) return false;
+    return true;
+  }
+  return c.n[0] <= kBlock;
+}
+
 int advect(sdc_handle h, const double* U, double* A, hipStream_t s) {
   const sdc_config& c = h->P.cfg;
   if (!c.advection) return fill(h, A, (int64_t)h->nc * h->P.Z, 0.0, s);
@@ -526,24 +577,15 @@ int advect(sdc_handle h, const double* U, double* A, hipStream_t s) {
   a.gamma = c.gamma;
   a.alpha = c.alpha;
   a.slope = c.slope;
+  if (h->f_advect_rows) {
+    a.rows = h->d_rows;
+    return launch_blocks(h, h->f_advect_rows, h->n_rows, &a, s);
+  }
   if (c.nbox > 0) {
     a.nbox = c.nbox;
     a.box_off = (const sdc_i64*)h->d_box_off;
     a.box_ext = h->d_box_ext;
     a.blk_box = h->d_blk_box;
-    return launch(h, h->f_advect, h->P.Z, &a, s);
-  }
-  if (h->f_advect_rows) {
-    // complete x-rows per block, each marching up a chunk of z planes; the
-    // chunk shrinks until the grid has at least 2048 blocks (or 4 planes)
-    const int64_t n0 = c.n[0], n1 = c.n[1], n2 = c.n[2];
-    const int64_t R = kBlock / n0;
-    int64_t zc = n2 < 32 ? n2 : 32;
-    auto blocks = [&](int64_t z) { return (n1 * ((n2 + z - 1) / z) + R - 1) / R; };
-    while (zc > 4 && blocks(zc) < 2048) zc /= 2;
-    a.rows = (int)R;
-    a.zchunk = (int)zc;
-    return launch_blocks(h, h->f_advect_rows, blocks(zc), &a, s);
   }
   return launch(h, h->f_advect, h->P.Z, &a, s);
 }
@@ -989,12 +1031,16 @@ int sdc_init(const sdc_config* cfg, const sdc_network* net, sdc_handle* out) {
   // 4 GiB (32-bit buffer offsets) use the row kernel (SDC_ADVECT_ROWS=0: the
   // zone-per-thread kernel everywhere)
   const char* ev = std::getenv("SDC_ADVECT_ROWS");
-  const sdc_config& gc = h->P.cfg;
-  if (gc.dim == 3 && gc.nbox == 0 && gc.n[0] <= kBlock && 8 * h->nc * h->P.Z < (int64_t(1) << 32) &&
-      !(ev && ev[0] == '0')) {
-    const char* name = gc.slope == 0 ? "sdc_advect_rows_c" : "sdc_advect_rows";
+  if (h->P.cfg.advection && rows_kernel_fits(h->P) && !(ev && ev[0] == '0')) {
+    const char* name = h->P.cfg.slope == 0 ? "sdc_advect_rows_c" : "sdc_advect_rows";
     e = hipModuleGetFunction(&h->f_advect_rows, h->mod, name);
     if (e != hipSuccess) return bail(SDC_ERR_HIP, std::string("missing kernel ") + name);
+    const std::vector<RowDesc> rows = row_descriptors(h->P);
+    h->n_rows = (int64_t)rows.size();
+    if (hipMalloc((void**)&h->d_rows, rows.size() * sizeof(RowDesc)) != hipSuccess)
+      return bail(SDC_ERR_NOMEM, "hipMalloc(row descriptors) failed");
+    if (hipMemcpy(h->d_rows, rows.data(), rows.size() * sizeof(RowDesc), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(SDC_ERR_HIP, "hipMemcpy(row descriptors) failed");
   }
   const std::vector<double> img = params_image(h->P, h->nra);
   e = hipMalloc(&h->d_params, img.size() * sizeof(double));
@@ -1046,6 +1092,7 @@ int sdc_destroy(sdc_handle h) {
   if (h->d_box_off) (void)hipFree(h->d_box_off);
   if (h->d_box_ext) (void)hipFree(h->d_box_ext);
   if (h->d_blk_box) (void)hipFree(h->d_blk_box);
+  if (h->d_rows) (void)hipFree(h->d_rows);
   if (h->d_stats) (void)hipFree(h->d_stats);
   if (h->mod) (void)hipModuleUnload(h->mod);
   delete h;
