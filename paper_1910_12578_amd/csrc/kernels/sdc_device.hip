@@ -269,6 +269,12 @@ __device__ __forceinline__ void st_at(__amdgpu_buffer_rsrc_t r, unsigned voff, u
 
 __device__ __forceinline__ int wrap_index(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// One component's values at a zone, its y neighbours y-2..y+2 and the two
+// planes above.
+struct Stencil7 {
+  double c, ym2, ym1, yp1, yp2, z1, z2;
+};
+
 template <int SLOPE>
 __device__ __forceinline__ double slope_t(double um, double u0, double up) {
   return SLOPE == 0 ? 0.5 * (up - um) : mc_slope_of(um, u0, up);
@@ -278,8 +284,8 @@ template <int SLOPE>
 __device__ __forceinline__ void advect_rows_body(const AdvArgs& a) {
   __shared__ double sh_u[SDC_NH][256];   // hydro components of the current plane
   __shared__ double sh_fh[SDC_NH][256];  // hydro x-face fluxes
-  __shared__ double sh_s[256];           // one species component
-  __shared__ double sh_fs[256];          // its x-face flux
+  __shared__ double sh_s[2][256];        // one species component (alternating)
+  __shared__ double sh_fs[2][256];       // its x-face flux (alternating)
   const unsigned b = xcd_block(blockIdx.x, gridDim.x);
   const RowDesc d = a.rows[b];
   const int n0 = d.n0, n1 = d.n1, n2 = d.n2, ZC = d.zc;
@@ -344,6 +350,18 @@ __device__ __forceinline__ void advect_rows_body(const AdvArgs& a) {
     const unsigned oc = (unsigned)kc * P8 + row8;
     const unsigned oz1 = (unsigned)wrap_index(kc + 1, n2) * P8 + row8;
     const unsigned oz2 = (unsigned)wrap_index(kc + 2, n2) * P8 + row8;
+    auto load7 = [&](int comp) {
+      const __amdgpu_buffer_rsrc_t rq = rU(comp);
+      Stencil7 v;
+      v.c = ld_at(rq, oc, 0);
+      v.ym2 = ld_at(rq, oc + oy[0], 0);
+      v.ym1 = ld_at(rq, oc + oy[1], 0);
+      v.yp1 = ld_at(rq, oc + oy[2], 0);
+      v.yp2 = ld_at(rq, oc + oy[3], 0);
+      v.z1 = ld_at(rq, oz1, 0);
+      v.z2 = ld_at(rq, oz2, 0);
+      return v;
+    };
     // ---- hydro: y and z faces from memory, stage the plane for x
     double Ay[SDC_NH], Az[SDC_NH];
     FaceHydro fy0, fy1, fz, fx;
@@ -379,6 +397,7 @@ __device__ __forceinline__ void advect_rows_body(const AdvArgs& a) {
         WLz[q] = WLzn[q];
       }
     }
+    Stencil7 nxt = load7(SDC_NH);  // first species, in flight across the hydro barriers
     __syncthreads();
     double Fx[SDC_NH];
     {
@@ -394,40 +413,50 @@ __device__ __forceinline__ void advect_rows_body(const AdvArgs& a) {
     }
 #pragma unroll
     for (int q = 0; q < SDC_NH; ++q) sh_fh[q][t] = Fx[q];
-    __syncthreads();
+    // ---- species, with the hydro faces' velocities and speeds.  One barrier
+    // per species: the barrier of species s publishes its staged values and
+    // the x-face flux of species s - 1 (the hydro fluxes for s = 0), in
+    // alternating LDS buffers; the loads of species s + 1 are issued before it.
+    double pf = 0.0, pay = 0.0, paz = 0.0;  // species s - 1: x flux, y and z parts
 #pragma unroll
-    for (int q = 0; q < SDC_NH; ++q) {
-      double acc = -((sh_fh[q][lxp1] - Fx[q]) * idx);
-      acc -= Ay[q];
-      acc -= Az[q];
-      if (act) st_at(rA(q), oc, 0, acc);
-    }
-    // ---- species, with the hydro faces' velocities and speeds
+    for (int s = 0; s <= SDC_NS; ++s) {
+      double c = 0.0, ay = 0.0, az = 0.0;
+      if (s < SDC_NS) {
+        const Stencil7 cur = nxt;
+        if (s + 1 < SDC_NS) nxt = load7(SDC_NH + s + 1);
+        c = cur.c;
+        sh_s[s & 1][t] = c;
+        const double sm = slope_t<SLOPE>(cur.ym2, cur.ym1, c), s0 = slope_t<SLOPE>(cur.ym1, c, cur.yp1);
+        const double sp = slope_t<SLOPE>(c, cur.yp1, cur.yp2), s1 = slope_t<SLOPE>(c, cur.z1, cur.z2);
+        ay = (species_face(c + 0.5 * s0, cur.yp1 - 0.5 * sp, fy1) - species_face(cur.ym1 + 0.5 * sm, c - 0.5 * s0, fy0)) * idy;
+        const double fzn = species_face(WLz[SDC_NH + s], cur.z1 - 0.5 * s1, fz);
+        az = (fzn - Fz[SDC_NH + s]) * idz;
+        Fz[SDC_NH + s] = fzn;
+        WLz[SDC_NH + s] = cur.z1 + 0.5 * s1;
+      }
+      __syncthreads();
+      if (s == 0) {
 #pragma unroll
-    for (int s = 0; s < SDC_NS; ++s) {
-      const __amdgpu_buffer_rsrc_t rq = rU(SDC_NH + s);
-      const double c = ld_at(rq, oc, 0);
-      sh_s[t] = c;
-      const double ym2 = ld_at(rq, oc + oy[0], 0), ym1 = ld_at(rq, oc + oy[1], 0);
-      const double yp1 = ld_at(rq, oc + oy[2], 0), yp2 = ld_at(rq, oc + oy[3], 0);
-      const double z1 = ld_at(rq, oz1, 0), z2 = ld_at(rq, oz2, 0);
-      const double sm = slope_t<SLOPE>(ym2, ym1, c), s0 = slope_t<SLOPE>(ym1, c, yp1);
-      const double sp = slope_t<SLOPE>(c, yp1, yp2), s1 = slope_t<SLOPE>(c, z1, z2);
-      const double ay = (species_face(c + 0.5 * s0, yp1 - 0.5 * sp, fy1) - species_face(ym1 + 0.5 * sm, c - 0.5 * s0, fy0)) * idy;
-      const double fzn = species_face(WLz[SDC_NH + s], z1 - 0.5 * s1, fz);
-      const double az = (fzn - Fz[SDC_NH + s]) * idz;
-      Fz[SDC_NH + s] = fzn;
-      WLz[SDC_NH + s] = z1 + 0.5 * s1;
-      __syncthreads();
-      const double xm2 = sh_s[lxm2], xm1 = sh_s[lxm1], xp1 = sh_s[lxp1];
-      const double sA = slope_t<SLOPE>(xm2, xm1, c), sB = slope_t<SLOPE>(xm1, c, xp1);
-      const double fxs = species_face(xm1 + 0.5 * sA, c - 0.5 * sB, fx);
-      sh_fs[t] = fxs;
-      __syncthreads();
-      double acc = -((sh_fs[lxp1] - fxs) * idx);
-      acc -= ay;
-      acc -= az;
-      if (act) st_at(rA(SDC_NH + s), oc, 0, acc);
+        for (int q = 0; q < SDC_NH; ++q) {
+          double acc = -((sh_fh[q][lxp1] - Fx[q]) * idx);
+          acc -= Ay[q];
+          acc -= Az[q];
+          if (act) st_at(rA(q), oc, 0, acc);
+        }
+      } else {
+        double acc = -((sh_fs[(s - 1) & 1][lxp1] - pf) * idx);
+        acc -= pay;
+        acc -= paz;
+        if (act) st_at(rA(SDC_NH + s - 1), oc, 0, acc);
+      }
+      if (s < SDC_NS) {
+        const double xm2 = sh_s[s & 1][lxm2], xm1 = sh_s[s & 1][lxm1], xp1 = sh_s[s & 1][lxp1];
+        const double sA = slope_t<SLOPE>(xm2, xm1, c), sB = slope_t<SLOPE>(xm1, c, xp1);
+        pf = species_face(xm1 + 0.5 * sA, c - 0.5 * sB, fx);
+        sh_fs[s & 1][t] = pf;
+        pay = ay;
+        paz = az;
+      }
     }
   }
 }
