@@ -87,8 +87,9 @@ def roofline(bytes_per_zone, flops_per_zone, zones, avg_s):
 
 def recorded_traffic(h, kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary,
-    if it was taken on the kernel source this handle compiled (else None)."""
-    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{kernel}_net3d_256cubed.md")
+    if it was taken on this kernel and on the source this handle compiled
+    (else None)."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_sdc_transition_node0_net3d_256cubed.md")
     if not os.path.exists(path):
         return None, None
     rec = {}
@@ -100,7 +101,7 @@ def recorded_traffic(h, kernel):
     import hashlib
     src = h.generated_source()
     digest = hashlib.sha256(src.encode()).hexdigest()[:16]
-    if rec.get("source_sha256_16") != digest or "traffic_bytes_per_launch" not in rec:
+    if rec.get("source_sha256_16") != digest or rec.get("kernel") != kernel or "traffic_bytes_per_launch" not in rec:
         return None, digest
     return float(rec["traffic_bytes_per_launch"]), digest
 
@@ -157,9 +158,10 @@ def run_gpu(w, precision, steps, warmup, schedule="auto"):
     dom = "transition_node0"
     avg = prof[dom][0] * 1e-3 / max(prof[dom][1], 1)
     roof = roofline(bpz[dom], fpz[dom], Z, avg)
-    traffic, digest = recorded_traffic(h, "sdc_" + dom)
+    kname = "sdc_" + dom + ("_o2" if sched["occ2"] else "")
+    traffic, digest = recorded_traffic(h, kname)
     roof["traffic"] = traffic
-    roof["kernel"] = "sdc_" + dom
+    roof["kernel"] = kname
     # whole step against the HBM roofline: every launch's algorithmic bytes
     step_bytes = sum(bpz[k] * Z * prof[k][1] for k in bpz if prof[k][1])
     res = dict(

@@ -237,7 +237,8 @@ int sdc_get_schedule(sdc_handle h, int32_t* occ2, int32_t* cap);
 /*
  * Time every schedule (occ2 in {0,1} x cap in {0,4,5,6}) on one SDC step from
  * U (read only; `work` is scratch) with HIP events on `stream`, keep the
- * fastest, and cache the choice on disk per kernel source and zone count.
+ * fastest (the default 0, 0 unless another is faster by more than 1%), and
+ * cache the choice on disk per kernel source and zone count.
  * Newton statistics are left unchanged.  Synchronises.
  */
 int sdc_autotune(sdc_handle h, double dt, const double* U, const sdc_nodes* work, void* stream);
