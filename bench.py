@@ -166,6 +166,7 @@ def run_gpu(w, precision, steps, warmup, schedule="auto"):
     step_bytes = sum(bpz[k] * Z * prof[k][1] for k in bpz if prof[k][1])
     res = dict(
         elapsed=elapsed, ms_per_step=1e3 * elapsed / steps, zone_updates=Z * steps / elapsed,
+        zone_sweeps=Z * steps * w["n_iters"] / elapsed,
         stats=st, mean_newton=st["iters"] / max(st["solves"] - st["failed"], 1), finite=ok,
         profile={k: dict(ms=round(v[0], 3), launches=v[1]) for k, v in prof.items() if v[1]},
         roofline=roof, step_hbm_frac=step_bytes / elapsed / (PEAK_HBM_GBS * 1e9),
@@ -249,23 +250,55 @@ def run_boxes(steps, warmup, precision, schedule="auto"):
     return out
 
 
-def cpu_baseline(w, edge):
-    """The oracle on an edge^3 corner of the same initial state, one step."""
+def _oracle_block(args):
+    """One oracle step on one sub-block (runs in a worker process)."""
+    light, U0, dt = args
     from threadpoolctl import threadpool_limits
     from oracle import sdc as osdc
-    dim = w["dim"]
-    sl = (slice(None),) + (slice(0, edge),) * dim
-    sub = dict(w, shape=(edge,) * dim)
-    U0 = np.ascontiguousarray(w["U0"][sl])
-    prob = osdc.Problem.from_workload(sub)
+    prob = osdc.Problem.from_workload(light)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        osdc.run(U0, w["dt"], 1, prob)
-        t = time.perf_counter() - t0
-    return dict(value=U0[0].size / t, unit="zone-updates/s", cores=1, kind="oracle",
-                sample=f"one step of a {edge}^{dim} corner of the same initial state "
-                       f"({U0[0].size} zones, same dt, network and iteration counts), NumPy FP64, "
-                       f"single thread, {t:.1f} s")
+        osdc.run(U0, dt, 1, prob)
+        return time.perf_counter() - t0
+
+
+def _warm_worker(_):
+    from oracle import sdc as osdc  # noqa: F401  (import cost outside the timed map)
+    return 0
+
+
+def cpu_baseline(w, edge, procs):
+    """The oracle, one step of edge^3 sub-blocks of the same initial state:
+    `procs` worker processes (one thread each) on distinct blocks at once,
+    and one block alone on one thread."""
+    import multiprocessing as mp
+    dim = w["dim"]
+    light = {k: v for k, v in w.items() if k != "U0"}
+    light["shape"] = (edge,) * dim
+    nb = w["shape"][0] // edge
+    blocks = []
+    for i in range(procs):
+        o = (i % nb, (i // nb) % nb, (i // nb // nb) % nb)[:dim]
+        sl = (slice(None),) + tuple(slice(c * edge, (c + 1) * edge) for c in o)
+        blocks.append((light, np.ascontiguousarray(w["U0"][sl]), w["dt"]))
+    zones = edge ** dim
+    t1 = _oracle_block(blocks[0])
+    out = dict(value=zones / t1, unit="zone-updates/s", cores=1, kind="oracle",
+               sample=f"one step of a {edge}^{dim} block of the same initial state ({zones} zones, same dt, "
+                      f"network and iteration counts), NumPy FP64, one thread: {t1:.1f} s")
+    if procs > 1:
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(procs) as pool:
+            pool.map(_warm_worker, range(procs))
+            t0 = time.perf_counter()
+            ts = pool.map(_oracle_block, blocks, chunksize=1)
+            wall = time.perf_counter() - t0
+        out = dict(value=procs * zones / wall, unit="zone-updates/s", cores=procs, kind="oracle",
+                   sample=f"{procs} processes of one thread, each one step of a different {edge}^{dim} block "
+                          f"of the same initial state ({zones} zones each, same dt, network and iteration "
+                          f"counts), NumPy FP64, wall {wall:.1f} s (slowest block {max(ts):.1f} s)",
+                   single_thread=out)
+    return out
 
 
 def main():
@@ -277,6 +310,8 @@ def main():
     ap.add_argument("--shape", default=None, help="override grid, e.g. 64,64,64")
     ap.add_argument("--precision", default="both", choices=("fp64", "mixed", "both"))
     ap.add_argument("--cpu-edge", type=int, default=48)
+    ap.add_argument("--cpu-procs", type=int, default=min(16, os.cpu_count() or 1),
+                    help="oracle worker processes for cpu_baseline (one thread each)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward time ratio")
     ap.add_argument("--boxes", action="store_true", help="also time the 4096-box batched workload")
@@ -315,6 +350,7 @@ def main():
                              f"K={w['n_iters']}", zones=Z, dt=w["dt"]),
         roofline=roof,
         step_hbm_frac=head["step_hbm_frac"],
+        zone_sweeps_per_s=head["zone_sweeps"],
         schedule=head["schedule"],
         mean_newton_iterations=head["mean_newton"],
         newton_failed=head["stats"]["failed"],
@@ -348,7 +384,7 @@ def main():
         del src, dst
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, a.cpu_edge)
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_edge, a.cpu_procs)
     print(json.dumps(out), flush=True)
 
 
