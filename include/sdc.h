@@ -224,20 +224,25 @@ int sdc_step_adjoint(sdc_handle h, double dt, const double* U_n, const double* U
                      double* thetabar, void* stream);
 
 /*
- * Kernel schedule of the Newton kernels: occ2 = 1 selects the variants built
- * for two wavefronts per SIMD (smaller register budget), occ2 = 0 the
- * compiler's budget; cap > 0 stops the fast Newton pass after `cap`
+ * Kernel schedule of the node transitions: occ2 = 1 selects the Newton
+ * variants built for two wavefronts per SIMD (smaller register budget), occ2
+ * = 0 the compiler's budget; cap > 0 stops the fast Newton pass after `cap`
  * iterations and finishes the zones still unconverged in a second kernel,
- * which packs the slow tail of the Newton counts into dense wavefronts
- * (cap = 0: no cap).  Every schedule produces bitwise-identical results.
+ * which packs the slow tail of the Newton counts into dense wavefronts (cap =
+ * 0: no cap); split > 0 cuts every transition into `split` zone batches whose
+ * explicit part (quadrature, rhs) runs in its own kernel on a second stream
+ * beside the Newton kernel of the previous batch (split = 0: one fused kernel
+ * per transition; captured steps always use the fused kernels).  Every
+ * schedule produces bitwise-identical results.  Returns SDC_ERR_ARG for occ2
+ * outside {0, 1}, cap < 0 or split outside [0, 64].
  */
-int sdc_set_schedule(sdc_handle h, int32_t occ2, int32_t cap);
-int sdc_get_schedule(sdc_handle h, int32_t* occ2, int32_t* cap);
+int sdc_set_schedule(sdc_handle h, int32_t occ2, int32_t cap, int32_t split);
+int sdc_get_schedule(sdc_handle h, int32_t* occ2, int32_t* cap, int32_t* split);
 
 /*
- * Time every schedule (occ2 in {0,1} x cap in {0,4,5,6}) on one SDC step from
+ * Time every fused schedule (occ2 in {0,1} x cap in {0,4,5,6}, split 0) on one SDC step from
  * U (read only; `work` is scratch) with HIP events on `stream`, keep the
- * fastest (the default 0, 0 unless another is faster by more than 1%), and
+ * fastest (the default 0, 0, 0 unless another is faster by more than 1%), and
  * cache the choice on disk per kernel source and zone count.
  * Newton statistics are left unchanged.  Synchronises.
  */
@@ -253,7 +258,8 @@ int sdc_autotune(sdc_handle h, double dt, const double* U, const sdc_nodes* work
 #define SDC_K_FILL 6
 #define SDC_K_ADJOINT 7  /* every kernel of the adjoint pass */
 #define SDC_K_FINISH 8   /* second-stage kernels of capped or guarded Newton solves */
-#define SDC_NKINDS 9
+#define SDC_K_SPLIT 9    /* batch kernels of the split schedule (each transition is also timed as one span) */
+#define SDC_NKINDS 10
 
 /*
  * Per-kernel timing: while enabled, every launch is bracketed by HIP events

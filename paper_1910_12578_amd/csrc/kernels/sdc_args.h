@@ -97,6 +97,10 @@ typedef struct {
   NewtonCtl ctl;
   unsigned long long* stats;
   DeferQueue q;
+  // split schedule: explicit part and Newton in separate kernels over a zone
+  // batch [zbeg, zbeg + zcount); `split` holds [NX + 2][Z]: b, KE, x_e guess
+  double* split;
+  sdc_i64 zbeg, zcount;
 } TransArgs;
 
 typedef struct {

@@ -856,15 +856,19 @@ __device__ __forceinline__ constexpr int react_index(int c) {
 
 // Finalise node m+1 of zone z: rho, rho u from the explicit part, rho E =
 // x_e + KE, rho X = x_s, and R^{m+1} re-evaluated at the root.
+// (FULL = false: rho and rho u were written by the explicit-part kernel.)
+template <bool FULL = true>
 __device__ __forceinline__ void transition_store(const TransArgs& a, i64 z, double rho, double ke, const double* mom,
                                                  const double* x, ParamPtr P) {
   const i64 Z = a.Z;
   double R[SDC_NX];
   net_source(x, 1.0 / rho, P, a.gm1, R);
   double* __restrict__ Uo = a.Uout;
-  Uo[z] = rho;
+  if (FULL) {
+    Uo[z] = rho;
 #pragma unroll
-  for (int d = 0; d < SDC_DIM; ++d) Uo[(i64)(1 + d) * Z + z] = mom[d];
+    for (int d = 0; d < SDC_DIM; ++d) Uo[(i64)(1 + d) * Z + z] = mom[d];
+  }
   Uo[(i64)(1 + SDC_DIM) * Z + z] = x[SDC_NX - 1] + ke;
 #pragma unroll
   for (int s = 0; s < SDC_NS; ++s) Uo[(i64)(SDC_NH + s) * Z + z] = x[s];
@@ -872,16 +876,15 @@ __device__ __forceinline__ void transition_store(const TransArgs& a, i64 z, doub
   for (int i = 0; i < SDC_NX; ++i) a.Rout[(i64)i * Z + z] = R[i];
 }
 
-template <class MT, int KIND>
-__device__ __forceinline__ void transition_body(const TransArgs& a) {
-  const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = z < a.Z;
-  ParamPtr P = stage_params(a.P);
+// Explicit part of the transition of zone z: the right-hand side of Eq. 2
+// (with the quadrature of every node and the C_m outputs for m = 0), the final
+// rho and rho u, KE at m+1, the reacting right-hand side b and the energy
+// component of the Newton guess (from the previous iterate of node m+1).
+template <int KIND>
+__device__ __forceinline__ void transition_explicit(const TransArgs& a, i64 z, double& rho, double& ke, double* mom,
+                                                    double* b, double& xe_guess) {
   const i64 Z = a.Z;
-  double rho = 1.0, ke = 0.0, mom[SDC_DIM];
-  double b[SDC_NX], x[SDC_NX];
-  int it = 0, st = 3;
-  if (valid) {
+  {
     double rhs[SDC_NC];
     if (KIND == KIND_FIRST) {
 #pragma unroll
@@ -919,6 +922,7 @@ __device__ __forceinline__ void transition_body(const TransArgs& a) {
     }
     // explicit part: rho and rho u are final
     rho = rhs[0];
+    ke = 0.0;
 #pragma unroll
     for (int d = 0; d < SDC_DIM; ++d) {
       mom[d] = rhs[1 + d];
@@ -928,7 +932,7 @@ __device__ __forceinline__ void transition_body(const TransArgs& a) {
 #pragma unroll
     for (int s = 0; s < SDC_NS; ++s) b[s] = rhs[SDC_NH + s];
     b[SDC_NX - 1] = rhs[1 + SDC_DIM] - ke;
-    // Newton guess: reacting vector of the previous iterate of node m+1
+    // energy part of the Newton guess: previous iterate of node m+1
     {
       const double* __restrict__ g = a.guess;
       const double grho = g[z];
@@ -939,10 +943,25 @@ __device__ __forceinline__ void transition_body(const TransArgs& a) {
         gke = fma(mo, mo, gke);
       }
       gke = 0.5 * gke / grho;
-#pragma unroll
-      for (int s = 0; s < SDC_NS; ++s) x[s] = g[(i64)(SDC_NH + s) * Z + z];
-      x[SDC_NX - 1] = g[(i64)(1 + SDC_DIM) * Z + z] - gke;
+      xe_guess = g[(i64)(1 + SDC_DIM) * Z + z] - gke;
     }
+  }
+}
+
+template <class MT, int KIND>
+__device__ __forceinline__ void transition_body(const TransArgs& a) {
+  const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = z < a.Z;
+  ParamPtr P = stage_params(a.P);
+  const i64 Z = a.Z;
+  double rho = 1.0, ke = 0.0, mom[SDC_DIM];
+  double b[SDC_NX], x[SDC_NX];
+  int it = 0, st = 3;
+  if (valid) {
+    transition_explicit<KIND>(a, z, rho, ke, mom, b, x[SDC_NX - 1]);
+    // species part of the Newton guess
+#pragma unroll
+    for (int s = 0; s < SDC_NS; ++s) x[s] = a.guess[(i64)(SDC_NH + s) * Z + z];
     it = newton_fast<MT>(x, b, 1.0 / rho, 1.0 / fabs(b[SDC_NX - 1]), a.dtm, P, a.gm1, a.ctl.tol, a.ctl.tau, 1,
                          min(a.ctl.cap, a.ctl.maxiter), st);
   }
@@ -995,6 +1014,89 @@ __device__ __forceinline__ void transition_finish_body(const TransArgs& a) {
     nonfinite = !all_finite(x);
   }
   stats_block(a.stats, nu, valid, nonfinite, fb);
+}
+
+// ---- split schedule.  The explicit part (quadrature, rhs, final rho and
+// rho u) of a zone batch runs in its own kernel, which streams through memory
+// with few registers, while the Newton kernel of the previous batch runs
+// beside it on another stream; the right-hand side b, KE and the energy part
+// of the guess pass through a [NX + 2][Z] array.  Same arithmetic as the
+// fused kernel, so the same bits.
+template <int KIND>
+__device__ __forceinline__ void transition_pre_body(const TransArgs& a) {
+  const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.zcount) return;
+  const i64 z = a.zbeg + t, Z = a.Z;
+  double rho, ke, mom[SDC_DIM], b[SDC_NX], xe;
+  transition_explicit<KIND>(a, z, rho, ke, mom, b, xe);
+  // the guess (previous iterate of node m+1, possibly this very array) has
+  // been read: rho and rho u of node m+1 are final
+  double* __restrict__ Uo = a.Uout;
+  Uo[z] = rho;
+#pragma unroll
+  for (int d = 0; d < SDC_DIM; ++d) Uo[(i64)(1 + d) * Z + z] = mom[d];
+#pragma unroll
+  for (int i = 0; i < SDC_NX; ++i) a.split[(i64)i * Z + z] = b[i];
+  a.split[(i64)SDC_NX * Z + z] = ke;
+  a.split[(i64)(SDC_NX + 1) * Z + z] = xe;
+}
+
+template <class MT>
+__device__ __forceinline__ void transition_newton_body(const TransArgs& a) {
+  const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = t < a.zcount;
+  const i64 z = a.zbeg + (valid ? t : 0), Z = a.Z;
+  ParamPtr P = stage_params(a.P);
+  double rho = 1.0, ke = 0.0;
+  double b[SDC_NX], x[SDC_NX];
+  int it = 0, st = 3;
+  if (valid) {
+    rho = a.Uout[z];
+    ke = a.split[(i64)SDC_NX * Z + z];
+#pragma unroll
+    for (int i = 0; i < SDC_NX; ++i) b[i] = a.split[(i64)i * Z + z];
+#pragma unroll
+    for (int s = 0; s < SDC_NS; ++s) x[s] = a.guess[(i64)(SDC_NH + s) * Z + z];
+    x[SDC_NX - 1] = a.split[(i64)(SDC_NX + 1) * Z + z];
+    it = newton_fast<MT>(x, b, 1.0 / rho, 1.0 / fabs(b[SDC_NX - 1]), a.dtm, P, a.gm1, a.ctl.tol, a.ctl.tau, 1,
+                         min(a.ctl.cap, a.ctl.maxiter), st);
+  }
+  const bool defer = valid && (st == 2 || (st == 1 && a.ctl.cap < a.ctl.maxiter));
+  const long long slot = defer_slot(a.q.count, defer);
+  int nu = 0;
+  bool nonfinite = false;
+  if (defer) {
+    const i64 cap = a.q.capacity;
+    a.q.z[slot] = z;
+    a.q.it[slot] = st == 2 ? -it : it;
+#pragma unroll
+    for (int i = 0; i < SDC_NX; ++i) {
+      a.q.x[(i64)i * cap + slot] = x[i];
+      a.q.b[(i64)i * cap + slot] = b[i];
+    }
+    a.q.aux[slot] = rho;
+    a.q.aux[cap + slot] = ke;
+#pragma unroll
+    for (int d = 0; d < SDC_DIM; ++d) a.q.aux[(i64)(2 + d) * cap + slot] = a.Uout[(i64)(1 + d) * Z + z];
+  } else if (valid) {
+    nu = st == 0 ? it : -1;
+    transition_store<false>(a, z, rho, ke, nullptr, x, P);
+    nonfinite = !all_finite(x);
+  }
+  stats_block(a.stats, nu, valid && !defer, nonfinite, 0);
+}
+
+// the explicit-part kernels share the CUs with the Newton kernel: few registers
+#define SDC_PRE __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+extern "C" __global__ SDC_PRE void sdc_transition_pre_first(TransArgs a) { transition_pre_body<KIND_FIRST>(a); }
+extern "C" __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void sdc_transition_pre_node0(
+    TransArgs a) {
+  transition_pre_body<KIND_NODE0>(a);
+}
+extern "C" __global__ SDC_PRE void sdc_transition_pre_later(TransArgs a) { transition_pre_body<KIND_LATER>(a); }
+extern "C" __global__ __launch_bounds__(256) void sdc_transition_newton(TransArgs a) { transition_newton_body<SdcMT>(a); }
+extern "C" __global__ __launch_bounds__(256) SDC_OCC2 void sdc_transition_newton_o2(TransArgs a) {
+  transition_newton_body<SdcMT>(a);
 }
 
 extern "C" __global__ __launch_bounds__(256) void sdc_transition_first(TransArgs a) { transition_body<SdcMT, KIND_FIRST>(a); }

@@ -373,7 +373,16 @@ struct sdc_handle_s {
   bool q_ready = false;
   int occ2 = 0;
   int cap = 0;  // 0: no cap (newton_maxiter)
+  // split schedule: zone batches whose explicit part (on `aux`) runs beside
+  // the Newton kernel of the previous batch; 0 = fused transition kernels
+  int split = 0;
   bool tuned = false;
+  bool capturing = false;
+  hipFunction_t f_pre[3] = {nullptr, nullptr, nullptr}, f_newton = nullptr, f_newton_o2 = nullptr;
+  hipStream_t aux = nullptr;
+  hipEvent_t fork_ev = nullptr;
+  std::vector<hipEvent_t> batch_ev;
+  double* split_buf = nullptr;  // [NX + 2][Z]
   hipFunction_t f_advect = nullptr, f_advect_rows = nullptr, f_source = nullptr, f_solve = nullptr, f_first = nullptr,
                 f_node0 = nullptr, f_later = nullptr, f_fill = nullptr;
   void* d_params = nullptr;
@@ -423,6 +432,8 @@ int kind_of(const sdc_handle h, hipFunction_t f) {
   if (f == h->f_solve) return SDC_K_SOLVE;
   if (f == h->f_solve_o2) return SDC_K_SOLVE;
   if (f == h->f_solve_finish || f == h->f_trans_finish) return SDC_K_FINISH;
+  if (f == h->f_pre[0] || f == h->f_pre[1] || f == h->f_pre[2] || f == h->f_newton || f == h->f_newton_o2)
+    return SDC_K_SPLIT;
   if (f == h->f_first || f == h->f_first_o2) return SDC_K_TRANSITION_FIRST;
   if (f == h->f_node0 || f == h->f_node0_o2) return SDC_K_TRANSITION_NODE0;
   if (f == h->f_later || f == h->f_later_o2) return SDC_K_TRANSITION_LATER;
@@ -497,6 +508,31 @@ int ensure_queue(sdc_handle h) {
     return fail(h, SDC_ERR_NOMEM, "hipMalloc(deferred-zone queue) failed");
   h->q_ready = true;
   return SDC_OK;
+}
+
+// Stream, events and the [NX + 2][Z] array of the split schedule.
+int ensure_split(sdc_handle h) {
+  if (!h->aux) HIP_CHECK(h, hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+  if (!h->fork_ev) HIP_CHECK(h, hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
+  while ((int)h->batch_ev.size() < h->split) {
+    hipEvent_t e = nullptr;
+    HIP_CHECK(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    h->batch_ev.push_back(e);
+  }
+  if (!h->split_buf && hipMalloc((void**)&h->split_buf, (size_t)(h->nx + 2) * h->P.Z * sizeof(double)) != hipSuccess)
+    return fail(h, SDC_ERR_NOMEM, "hipMalloc(split schedule array) failed");
+  return SDC_OK;
+}
+
+void free_split(sdc_handle h) {
+  if (h->split_buf) (void)hipFree(h->split_buf);
+  for (auto e : h->batch_ev) (void)hipEventDestroy(e);
+  if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+  if (h->aux) (void)hipStreamDestroy(h->aux);
+  h->split_buf = nullptr;
+  h->batch_ev.clear();
+  h->fork_ev = nullptr;
+  h->aux = nullptr;
 }
 
 void free_queue(sdc_handle h) {
@@ -604,6 +640,51 @@ bool nodes_ok(const sdc_handle h, const sdc_nodes* n, bool need_c) {
   return true;
 }
 
+// One node transition in the split schedule: the explicit-part kernels of
+// the zone batches run in order on the auxiliary stream, each Newton batch on
+// `s` waits for its own explicit part only, so batch i's Newton overlaps batch
+// i+1's explicit part; the finish kernel follows the last batch.  With
+// profiling on, the whole transition is timed as one span of its kind.
+int split_transition(sdc_handle h, int kind, TransArgs a, hipStream_t s) {
+  if (int rc = ensure_split(h)) return rc;
+  const int64_t Z = h->P.Z, nb = h->split;
+  const int64_t B = (Z + nb - 1) / nb;
+  a.split = h->split_buf;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const bool prof = h->profile;
+  if (prof) {
+    e0 = take_event(h);
+    e1 = take_event(h);
+    if (!e0 || !e1) return fail(h, SDC_ERR_HIP, "hipEventCreate failed");
+    HIP_CHECK(h, hipEventRecord(e0, s));
+  }
+  HIP_CHECK(h, hipEventRecord(h->fork_ev, s));
+  HIP_CHECK(h, hipStreamWaitEvent(h->aux, h->fork_ev, 0));
+  int64_t n = 0;
+  for (int64_t i = 0; i < nb && i * B < Z; ++i, ++n) {
+    a.zbeg = i * B;
+    a.zcount = std::min<int64_t>(B, Z - a.zbeg);
+    if (int rc = launch(h, h->f_pre[kind], a.zcount, &a, h->aux)) return rc;
+    HIP_CHECK(h, hipEventRecord(h->batch_ev[i], h->aux));
+  }
+  hipFunction_t fn = h->occ2 ? h->f_newton_o2 : h->f_newton;
+  for (int64_t i = 0; i < n; ++i) {
+    a.zbeg = i * B;
+    a.zcount = std::min<int64_t>(B, Z - a.zbeg);
+    HIP_CHECK(h, hipStreamWaitEvent(s, h->batch_ev[i], 0));
+    if (int rc = launch(h, fn, a.zcount, &a, s)) return rc;
+  }
+  h->profile = false;  // the finish kernel is part of the span
+  int rc = launch(h, h->f_trans_finish, Z, &a, s);
+  h->profile = prof;
+  if (rc) return rc;
+  if (prof) {
+    HIP_CHECK(h, hipEventRecord(e1, s));
+    h->timed.push_back({SDC_K_TRANSITION_FIRST + kind, e0, e1});
+  }
+  return SDC_OK;
+}
+
 // One iteration k -> k+1 over the M transitions, then A at node M.
 int sweep(sdc_handle h, double dt, int k, const sdc_nodes& n, hipStream_t s) {
   const int M = h->M;
@@ -637,12 +718,18 @@ int sweep(sdc_handle h, double dt, int k, const sdc_nodes& n, hipStream_t s) {
     a.ctl = newton_ctl(h);
     a.stats = h->d_stats;
     a.q = h->q;
-    hipFunction_t f = k == 0 ? (h->occ2 ? h->f_first_o2 : h->f_first)
-                             : (m == 0 ? (h->occ2 ? h->f_node0_o2 : h->f_node0) : (h->occ2 ? h->f_later_o2 : h->f_later));
+    const int kind = k == 0 ? 0 : (m == 0 ? 1 : 2);
     int rc = reset_queue(h, s);
     if (rc) return rc;
-    if ((rc = launch(h, f, h->P.Z, &a, s))) return rc;
-    if ((rc = launch(h, h->f_trans_finish, h->P.Z, &a, s))) return rc;
+    if (h->split > 0 && !h->capturing) {
+      if ((rc = split_transition(h, kind, a, s))) return rc;
+    } else {
+      hipFunction_t f = kind == 0 ? (h->occ2 ? h->f_first_o2 : h->f_first)
+                                  : (kind == 1 ? (h->occ2 ? h->f_node0_o2 : h->f_node0)
+                                               : (h->occ2 ? h->f_later_o2 : h->f_later));
+      if ((rc = launch(h, f, h->P.Z, &a, s))) return rc;
+      if ((rc = launch(h, h->f_trans_finish, h->P.Z, &a, s))) return rc;
+    }
     if (h->P.cfg.advection) {
       rc = advect(h, n.U[m + 1], n.A[m + 1], s);
       if (rc) return rc;
@@ -667,7 +754,9 @@ int capture_step(sdc_handle h, double dt, const sdc_nodes& n, hipGraphExec_t* ou
   if (!h->capture_stream) HIP_CHECK(h, hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
   HIP_CHECK(h, hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
   int rc = SDC_OK;
+  h->capturing = true;  // a captured step uses the fused transition kernels
   for (int k = 0; k < h->P.cfg.n_iters && rc == SDC_OK; ++k) rc = sweep(h, dt, k, n, h->capture_stream);
+  h->capturing = false;
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(h->capture_stream, &g);
   if (rc) {
@@ -847,17 +936,18 @@ int step_adjoint(sdc_handle h, double dt, const double* Un, const double* Ubar1,
 std::string tune_path(const sdc_handle h) {
   const sdc_config& c = h->P.cfg;
   char name[128];
-  std::snprintf(name, sizeof name, "tune_%016llx_z%lld_k%d_a%d.txt", (unsigned long long)fnv1a(h->P.source),
+  std::snprintf(name, sizeof name, "tune3_%016llx_z%lld_k%d_a%d.txt", (unsigned long long)fnv1a(h->P.source),
                 (long long)h->P.Z, (int)c.n_iters, (int)c.advection);
   return cache_dir() + "/" + name;
 }
 
 bool load_tuning(sdc_handle h) {
   std::ifstream f(tune_path(h));
-  int o = -1, c = -1;
-  if (!(f >> o >> c) || o < 0 || o > 1 || c < 0) return false;
+  int o = -1, c = -1, sp = -1;
+  if (!(f >> o >> c >> sp) || o < 0 || o > 1 || c < 0 || sp < 0 || sp > 64) return false;
   h->occ2 = o;
   h->cap = c;
+  h->split = sp;
   h->tuned = true;
   return true;
 }
@@ -879,14 +969,18 @@ int autotune(sdc_handle h, double dt, const double* U, const sdc_nodes& n, hipSt
   hipEvent_t e0, e1;
   HIP_CHECK(h, hipEventCreate(&e0));
   HIP_CHECK(h, hipEventCreate(&e1));
-  const int caps[] = {0, 4, 5, 6};
+  // the split schedule is not searched: it moves more bytes and measured
+  // slower than the fused kernels on the 3D workloads
+  const int caps[] = {0, 4, 5, 6}, splits[] = {0};
   float best = 1e30f;
-  int bo = 0, bc = 0;
+  int bo = 0, bc = 0, bs = 0;
   for (int rep = 0; rep < 2 && rc == SDC_OK; ++rep)  // the first pass warms caches and clocks
+    for (int sp : splits)
     for (int o = 0; o < 2 && rc == SDC_OK; ++o)
       for (int c : caps) {
         h->occ2 = o;
         h->cap = c;
+        h->split = sp;
         if ((rc = (hipEventRecord(e0, s) == hipSuccess ? SDC_OK : SDC_ERR_HIP))) break;
         for (int k = 0; k < h->P.cfg.n_iters && rc == SDC_OK; ++k) rc = sweep(h, dt, k, n, s);
         if (rc) break;
@@ -898,10 +992,11 @@ int autotune(sdc_handle h, double dt, const double* U, const sdc_nodes& n, hipSt
         (void)hipEventElapsedTime(&ms, e0, e1);
         // the default schedule (tried first) is replaced only by one that is
         // faster by more than 1%, so equal variants do not flip between runs
-        if (rep == 1 && ms < (o == 0 && c == 0 ? best : 0.99f * best)) {
+        if (rep == 1 && ms < (o == 0 && c == 0 && sp == 0 ? best : 0.99f * best)) {
           best = ms;
           bo = o;
           bc = c;
+          bs = sp;
         }
       }
   (void)hipEventDestroy(e0);
@@ -910,11 +1005,12 @@ int autotune(sdc_handle h, double dt, const double* U, const sdc_nodes& n, hipSt
   if (rc) return rc;
   h->occ2 = bo;
   h->cap = bc;
+  h->split = bs;
   h->tuned = true;
   drop_graphs(h);
   HIP_CHECK(h, hipMemcpy(h->d_stats, saved, sizeof saved, hipMemcpyHostToDevice));
   const std::string path = tune_path(h);
-  std::string text = std::to_string(bo) + " " + std::to_string(bc) + "\n";
+  std::string text = std::to_string(bo) + " " + std::to_string(bc) + " " + std::to_string(bs) + "\n";
   std::vector<char> data(text.begin(), text.end());
   const auto k = path.rfind('/');
   write_file_atomic(path.substr(0, k), path.substr(k + 1), data);
@@ -1024,6 +1120,9 @@ int sdc_init(const sdc_config* cfg, const sdc_network* net, sdc_handle* out) {
              {&h->f_axpy, "sdc_axpy"}, {&h->f_first_o2, "sdc_transition_first_o2"},
              {&h->f_node0_o2, "sdc_transition_node0_o2"}, {&h->f_later_o2, "sdc_transition_later_o2"},
              {&h->f_trans_finish, "sdc_transition_finish"}, {&h->f_solve_o2, "sdc_reaction_solve_o2"},
+             {&h->f_pre[0], "sdc_transition_pre_first"}, {&h->f_pre[1], "sdc_transition_pre_node0"},
+             {&h->f_pre[2], "sdc_transition_pre_later"}, {&h->f_newton, "sdc_transition_newton"},
+             {&h->f_newton_o2, "sdc_transition_newton_o2"},
              {&h->f_solve_finish, "sdc_reaction_finish"}, {&h->f_reset, "sdc_reset_counter"}};
   for (auto& fn : fns) {
     e = hipModuleGetFunction(fn.f, h->mod, fn.name);
@@ -1090,6 +1189,7 @@ int sdc_destroy(sdc_handle h) {
   if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
   for (double* p : h->adj_buf) (void)hipFree(p);
   free_queue(h);
+  free_split(h);
   if (h->d_params) (void)hipFree(h->d_params);
   if (h->d_box_off) (void)hipFree(h->d_box_off);
   if (h->d_box_ext) (void)hipFree(h->d_box_ext);
@@ -1243,20 +1343,23 @@ int sdc_step_adjoint(sdc_handle h, double dt, const double* U_n, const double* U
   return step_adjoint(h, dt, U_n, Ubar_np1, Ubar_n, thetabar, s);
 }
 
-int sdc_set_schedule(sdc_handle h, int32_t occ2, int32_t cap) {
+int sdc_set_schedule(sdc_handle h, int32_t occ2, int32_t cap, int32_t split) {
   if (int rc = check_handle(h)) return rc;
-  if (occ2 < 0 || occ2 > 1 || cap < 0) return fail(h, SDC_ERR_ARG, "occ2 must be 0 or 1 and cap >= 0");
+  if (occ2 < 0 || occ2 > 1 || cap < 0 || split < 0 || split > 64)
+    return fail(h, SDC_ERR_ARG, "occ2 must be 0 or 1, cap >= 0 and 0 <= split <= 64");
   h->occ2 = occ2;
   h->cap = cap;
+  h->split = split;
   h->tuned = true;
   drop_graphs(h);
   return SDC_OK;
 }
 
-int sdc_get_schedule(sdc_handle h, int32_t* occ2, int32_t* cap) {
+int sdc_get_schedule(sdc_handle h, int32_t* occ2, int32_t* cap, int32_t* split) {
   if (int rc = check_handle(h)) return rc;
   if (occ2) *occ2 = h->occ2;
   if (cap) *cap = h->cap;
+  if (split) *split = h->split;
   return SDC_OK;
 }
 

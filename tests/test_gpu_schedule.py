@@ -14,7 +14,7 @@ from tests.test_gpu_parity import make
 
 pytestmark = pytest.mark.gpu
 
-SCHEDULES = [(1, 0), (0, 1), (1, 2), (0, 3), (1, 4), (0, 6)]
+SCHEDULES = [(1, 0, 0), (0, 1, 0), (1, 2, 0), (0, 3, 0), (1, 4, 0), (0, 6, 0), (0, 0, 8), (1, 0, 3), (0, 2, 5)]
 
 
 def one_step(h, w, nsteps=1):
@@ -30,13 +30,13 @@ def one_step(h, w, nsteps=1):
 def test_step_schedules_bitwise_identical(name, precision):
     w, prob, h = make(name, precision=precision)
     ref, sref = one_step(h, w, 2)
-    for occ2, cap in SCHEDULES:
-        h.set_schedule(occ2, cap)
-        assert h.schedule() == (occ2, cap)
+    for occ2, cap, split in SCHEDULES:
+        h.set_schedule(occ2, cap, split)
+        assert h.schedule() == (occ2, cap, split)
         U, s = one_step(h, w, 2)
-        print(f"{name} p{precision} occ2={occ2} cap={cap}: identical={bool((U == ref).all())}")
-        assert bool((U == ref).all()), (occ2, cap)
-        assert s == sref, (occ2, cap)
+        print(f"{name} p{precision} occ2={occ2} cap={cap} split={split}: identical={bool((U == ref).all())}")
+        assert bool((U == ref).all()), (occ2, cap, split)
+        assert s == sref, (occ2, cap, split)
 
 
 @pytest.mark.parametrize("cap", [1, 2, 5])
@@ -68,6 +68,42 @@ def test_pivot_fallback_through_the_finish_kernel():
     assert s["fallbacks"] == s["solves"] and s["failed"] == 0
 
 
+@pytest.mark.parametrize("split", [1, 4])
+def test_pivot_fallback_in_split_schedule(split):
+    """Guard failures deferred from the Newton kernel of the split schedule
+    (rho u read back from node m+1) match the oracle."""
+    w, prob, h = make("net2d", pivot_threshold=2.0)
+    h.set_schedule(0, 0, split)
+    U0 = w["U0"]
+    nc = U0.shape[0]
+    Ug = to_gpu(U0.reshape(nc, -1))
+    h.step(w["dt"], 1, Ug)
+    ref = osdc.run(U0, w["dt"], 1, prob).reshape(nc, -1)
+    e = rel_err_per_component(to_np(Ug), ref)
+    assert np.all(e <= TOL_FP64), e
+    s = h.stats()
+    assert s["fallbacks"] == s["solves"] and s["failed"] == 0
+
+
+def test_graph_replay_with_split_schedule():
+    """A captured step uses the fused kernels; eager steps of the split
+    schedule give the same bits, replay after replay."""
+    import torch
+    w, prob, hg = make("net2d", graph=1)
+    _, _, he = make("net2d", graph=0)
+    hg.set_schedule(0, 0, 4)
+    he.set_schedule(0, 0, 4)
+    nc = w["U0"].shape[0]
+    a = to_gpu(w["U0"].reshape(nc, -1))
+    b = a.clone()
+    wa, wb = hg.alloc_nodes(), he.alloc_nodes()
+    for rep in range(3):
+        hg.step(w["dt"], 2, a, wa)
+        he.step(w["dt"], 2, b, wb)
+        torch.cuda.synchronize()
+        assert bool((a == b).all()), f"replay {rep} differs"
+
+
 def test_unconverged_zones_with_cap():
     w, prob, h = make("net2d", newton_maxiter=2)
     rho, _, x0, _ = osdc.split_state(w["U0"], prob)
@@ -89,6 +125,8 @@ def test_bad_schedule_raises():
         h.set_schedule(2, 0)
     with pytest.raises(SDCError):
         h.set_schedule(0, -1)
+    with pytest.raises(SDCError):
+        h.set_schedule(0, 0, 65)
 
 
 def test_autotune_keeps_results_and_stats():
@@ -97,9 +135,9 @@ def test_autotune_keeps_results_and_stats():
     nc = w["U0"].shape[0]
     U = to_gpu(w["U0"].reshape(nc, -1))
     h.stats_reset()
-    occ2, cap = h.autotune(w["dt"], U)
-    print(f"autotuned schedule: occ2={occ2} cap={cap}")
-    assert occ2 in (0, 1) and cap in (0, 4, 5, 6)
+    occ2, cap, split = h.autotune(w["dt"], U)
+    print(f"autotuned schedule: occ2={occ2} cap={cap} split={split}")
+    assert occ2 in (0, 1) and cap in (0, 4, 5, 6) and split == 0
     assert h.stats()["solves"] == 0
     assert bool((U == to_gpu(w["U0"].reshape(nc, -1))).all())  # input untouched
     U2, s2 = one_step(h, w)
