@@ -621,11 +621,16 @@ __device__ __forceinline__ int newton_fast(double* x, double* b, double irho, do
     double G[SDC_NX];
     MT M[SDC_NNZ];
     net_residual_matrix<MT>(xs, bs, irho, dtm, P, gm1, G, M);
+    MT r[SDC_NX];
     if constexpr (sizeof(MT) == sizeof(double)) {
       // an FP64 matrix leaves no room for the residual during the factorisation
 #pragma unroll
       for (int i = 0; i < SDC_NX; ++i) gs.set(i, G[i]);
       asm volatile("" ::: "memory");
+    } else {
+      // the mixed mode carries the rounded right-hand side (half the registers)
+#pragma unroll
+      for (int i = 0; i < SDC_NX; ++i) r[i] = (MT)(-G[i]);
     }
     if (!net_lu<MT>(M, (MT)tau)) {
       st = 2;
@@ -634,11 +639,8 @@ __device__ __forceinline__ int newton_fast(double* x, double* b, double irho, do
     if constexpr (sizeof(MT) == sizeof(double)) {
       asm volatile("" ::: "memory");
 #pragma unroll
-      for (int i = 0; i < SDC_NX; ++i) G[i] = gs.get(i);
+      for (int i = 0; i < SDC_NX; ++i) r[i] = (MT)(-gs.get(i));
     }
-    MT r[SDC_NX];
-#pragma unroll
-    for (int i = 0; i < SDC_NX; ++i) r[i] = (MT)(-G[i]);
     net_solve<MT>(M, r);
     asm volatile("" ::: "memory");
     double err = 0.0, inf_or_nan = ise * 0.0;  // fmax drops NaN, so track it apart
