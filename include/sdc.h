@@ -24,7 +24,9 @@
  *    components: (rho X_1 .. rho X_nspec, rho e); the last one acts on rho E.
  *  - The caller owns every array passed in; the library never frees or
  *    reallocates them.  The handle owns its own device buffers (network
- *    parameters, statistics counters, cached graphs).
+ *    parameters, statistics counters, the deferred-zone queue of the Newton
+ *    kernels, advection row descriptors, cached graphs, and the workspaces of
+ *    the adjoint and of the split schedule, allocated on first use).
  *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL = the
  *    default stream).  The return code reports argument validation and launch
  *    errors only; device-side outcomes (unconverged or non-finite zones) are
@@ -113,8 +115,9 @@ typedef struct {
   /* 1: sdc_step replays one captured HIP graph per step (per buffer-rotation
    * phase); 0 (default): plain launches.  Profiling forces launches. */
   int32_t graph;
-  /* 1: the first sdc_step call runs sdc_autotune on its input; 0 (default):
-   * use the schedule set with sdc_set_schedule or the cached tuning. */
+  /* 1: the first sdc_step call takes the schedule cached on disk for this
+   * kernel source and size, or runs sdc_autotune on its input; 0 (default):
+   * the schedule set with sdc_set_schedule (initially 0, 0, 0). */
   int32_t autotune;
 } sdc_config;
 
@@ -240,11 +243,11 @@ int sdc_set_schedule(sdc_handle h, int32_t occ2, int32_t cap, int32_t split);
 int sdc_get_schedule(sdc_handle h, int32_t* occ2, int32_t* cap, int32_t* split);
 
 /*
- * Time every fused schedule (occ2 in {0,1} x cap in {0,4,5,6}, split 0) on one SDC step from
- * U (read only; `work` is scratch) with HIP events on `stream`, keep the
- * fastest (the default 0, 0, 0 unless another is faster by more than 1%), and
- * cache the choice on disk per kernel source and zone count.
- * Newton statistics are left unchanged.  Synchronises.
+ * Time every fused schedule (occ2 in {0,1} x cap in {0,4,5,6}, split 0) on
+ * one SDC step from U (read only; `work` is scratch) with HIP events on
+ * `stream`, keep the fastest (the default 0, 0, 0 unless another is faster by
+ * more than 1%), and cache the choice on disk per kernel source and zone
+ * count.  Newton statistics are left unchanged.  Synchronises.
  */
 int sdc_autotune(sdc_handle h, double dt, const double* U, const sdc_nodes* work, void* stream);
 
