@@ -127,8 +127,9 @@ def warm(h, dt, U, work, warmup, schedule):
     elif schedule == "auto":
         h.autotune(dt, U, work)
     torch.cuda.synchronize()
-    occ2, cap, split = h.schedule()
-    return dict(occ2=occ2, cap=cap, split=split, mode=schedule, warmup_s=round(time.perf_counter() - t0, 3))
+    occ2, cap, split, zchunk = h.schedule()
+    return dict(occ2=occ2, cap=cap, split=split, zchunk=zchunk, mode=schedule,
+                warmup_s=round(time.perf_counter() - t0, 3))
 
 
 def run_gpu(w, precision, steps, warmup, schedule="auto"):
@@ -316,7 +317,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward time ratio")
     ap.add_argument("--boxes", action="store_true", help="also time the 4096-box batched workload")
     ap.add_argument("--schedule", default="auto",
-                    help="transition schedule: 'auto' (tuned on the first warmup step) or 'OCC2,CAP[,SPLIT]', e.g. 0,0,8")
+                    help="schedule: 'auto' (tuned on the first warmup step) or 'OCC2,CAP[,SPLIT[,ZCHUNK]]', e.g. 0,0,0,16")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (calibrates HBM byte counters)")
     a = ap.parse_args()

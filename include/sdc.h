@@ -117,7 +117,7 @@ typedef struct {
   int32_t graph;
   /* 1: the first sdc_step call takes the schedule cached on disk for this
    * kernel source and size, or runs sdc_autotune on its input; 0 (default):
-   * the schedule set with sdc_set_schedule (initially 0, 0, 0). */
+   * the schedule set with sdc_set_schedule (initially 0, 0, 0, 0). */
   int32_t autotune;
 } sdc_config;
 
@@ -235,19 +235,23 @@ int sdc_step_adjoint(sdc_handle h, double dt, const double* U_n, const double* U
  * 0: no cap); split > 0 cuts every transition into `split` zone batches whose
  * explicit part (quadrature, rhs) runs in its own kernel on a second stream
  * beside the Newton kernel of the previous batch (split = 0: one fused kernel
- * per transition; captured steps always use the fused kernels).  Every
- * schedule produces bitwise-identical results.  Returns SDC_ERR_ARG for occ2
- * outside {0, 1}, cap < 0 or split outside [0, 64].
+ * per transition; captured steps always use the fused kernels); zchunk > 0
+ * sets the tile of the 3D row advection kernel, the number of z planes one
+ * row marches (0: chosen from the grid size).  Every schedule produces
+ * bitwise-identical results.  Returns SDC_ERR_ARG for occ2 outside {0, 1},
+ * cap < 0, split outside [0, 64] or zchunk outside [0, 1024].  A new zchunk
+ * synchronises the handle's last stream (the tile table is rewritten).
  */
-int sdc_set_schedule(sdc_handle h, int32_t occ2, int32_t cap, int32_t split);
-int sdc_get_schedule(sdc_handle h, int32_t* occ2, int32_t* cap, int32_t* split);
+int sdc_set_schedule(sdc_handle h, int32_t occ2, int32_t cap, int32_t split, int32_t zchunk);
+int sdc_get_schedule(sdc_handle h, int32_t* occ2, int32_t* cap, int32_t* split, int32_t* zchunk);
 
 /*
  * Time every fused schedule (occ2 in {0,1} x cap in {0,4,5,6}, split 0) on
  * one SDC step from U (read only; `work` is scratch) with HIP events on
- * `stream`, keep the fastest (the default 0, 0, 0 unless another is faster by
- * more than 1%), and cache the choice on disk per kernel source and zone
- * count.  Newton statistics are left unchanged.  Synchronises.
+ * `stream`, then the row-kernel tile (zchunk in {0, 16, 32, 64, 128}) on the
+ * advective term of U; keep the fastest of each (the defaults unless another
+ * is faster by more than 1%), and cache the choice on disk per kernel source
+ * and zone count.  Newton statistics are left unchanged.  Synchronises.
  */
 int sdc_autotune(sdc_handle h, double dt, const double* U, const sdc_nodes* work, void* stream);
 

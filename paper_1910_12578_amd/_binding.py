@@ -90,8 +90,9 @@ def lib():
         L.sdc_profile_read.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int64)]
         L.sdc_cost_model.argtypes = [c_void_p, POINTER(c_int64)]
         L.sdc_step_adjoint.argtypes = [c_void_p, c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
-        L.sdc_set_schedule.argtypes = [c_void_p, c_int32, c_int32, c_int32]
-        L.sdc_get_schedule.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)]
+        L.sdc_set_schedule.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_int32]
+        L.sdc_get_schedule.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
+                                       POINTER(c_int32)]
         L.sdc_autotune.argtypes = [c_void_p, c_double, c_void_p, POINTER(Nodes), c_void_p]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype or c_int
@@ -302,13 +303,14 @@ class SDC:
         """The device source this handle compiled (generated network code + kernels)."""
         return generated_source(self.cfg, self.net)
 
-    def set_schedule(self, occ2, cap, split=0):
-        _check(lib().sdc_set_schedule(self._h, int(occ2), int(cap), int(split)), self._h)
+    def set_schedule(self, occ2, cap, split=0, zchunk=0):
+        _check(lib().sdc_set_schedule(self._h, int(occ2), int(cap), int(split), int(zchunk)), self._h)
 
     def schedule(self):
-        o, c, sp = c_int32(), c_int32(), c_int32()
-        _check(lib().sdc_get_schedule(self._h, byref(o), byref(c), byref(sp)), self._h)
-        return o.value, c.value, sp.value
+        """(occ2, cap, split, zchunk)"""
+        o, c, sp, zt = c_int32(), c_int32(), c_int32(), c_int32()
+        _check(lib().sdc_get_schedule(self._h, byref(o), byref(c), byref(sp), byref(zt)), self._h)
+        return o.value, c.value, sp.value, zt.value
 
     def autotune(self, dt, U, work=None, stream=None):
         work = self.alloc_nodes() if work is None else work

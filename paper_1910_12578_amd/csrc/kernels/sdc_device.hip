@@ -109,8 +109,26 @@ __device__ __forceinline__ void hydro_flux(const double* W, int d, double gamma,
   c = sqrt(gamma * p * ir);
 #pragma unroll
   for (int q = 0; q < SDC_NH; ++q) F[q] = W[q] * un;
-  F[1 + d] += p;
-  F[1 + SDC_DIM] += p * un;
+  // multiply-adds written out, so every kernel rounds a face the same way
+  F[1 + d] = fma(W[1 + d], un, p);
+  F[1 + SDC_DIM] = fma(p, un, F[1 + SDC_DIM]);
+}
+
+// Rusanov flux of the hydro components through one face from the two
+// reconstructed states, plus the face data the species fluxes need.
+__device__ __forceinline__ void hydro_face(const double* WL, const double* WR, int d, double gamma, double alpha,
+                                           double* F, FaceHydro& fh) {
+  double FL[SDC_NH], FR[SDC_NH], pL, pR, cL, cR;
+  hydro_flux(WL, d, gamma, FL, fh.uL, pL, cL);
+  hydro_flux(WR, d, gamma, FR, fh.uR, pR, cR);
+  fh.a = alpha > 0.0 ? alpha : fmax(fabs(fh.uL) + cL, fabs(fh.uR) + cR);
+  const double ha = -0.5 * fh.a;
+#pragma unroll
+  for (int q = 0; q < SDC_NH; ++q) F[q] = fma(ha, WR[q] - WL[q], 0.5 * (FL[q] + FR[q]));
+}
+
+__device__ __forceinline__ double species_face(double L, double R, const FaceHydro& f) {
+  return fma(-0.5 * f.a, R - L, 0.5 * fma(L, f.uL, R * f.uR));
 }
 
 extern "C" __global__ __launch_bounds__(256) void sdc_advect(AdvArgs a) {
@@ -180,14 +198,7 @@ extern "C" __global__ __launch_bounds__(256) void sdc_advect(AdvArgs a) {
     }
     double Fh[2][SDC_NH];
 #pragma unroll
-    for (int f = 0; f < 2; ++f) {
-      double FL[SDC_NH], FR[SDC_NH], pL, pR, cL, cR;
-      hydro_flux(WL[f], d, a.gamma, FL, fh[d][f].uL, pL, cL);
-      hydro_flux(WR[f], d, a.gamma, FR, fh[d][f].uR, pR, cR);
-      fh[d][f].a = a.alpha > 0.0 ? a.alpha : fmax(fabs(fh[d][f].uL) + cL, fabs(fh[d][f].uR) + cR);
-#pragma unroll
-      for (int q = 0; q < SDC_NH; ++q) Fh[f][q] = 0.5 * (FL[q] + FR[q]) - 0.5 * fh[d][f].a * (WR[f][q] - WL[f][q]);
-    }
+    for (int f = 0; f < 2; ++f) hydro_face(WL[f], WR[f], d, a.gamma, a.alpha, Fh[f], fh[d][f]);
     const double id = a.idx[d];
 #pragma unroll
     for (int q = 0; q < SDC_NH; ++q) acc[q] -= (Fh[1][q] - Fh[0][q]) * id;
@@ -206,35 +217,12 @@ extern "C" __global__ __launch_bounds__(256) void sdc_advect(AdvArgs a) {
       const double sm = slope_of(v0, v1, v2, a.slope);
       const double s0 = slope_of(v1, v2, v3, a.slope);
       const double sp = slope_of(v2, v3, v4, a.slope);
-      double F0, F1;
-      {
-        const double L = v1 + 0.5 * sm, R = v2 - 0.5 * s0;
-        F0 = 0.5 * (L * fh[d][0].uL + R * fh[d][0].uR) - 0.5 * fh[d][0].a * (R - L);
-      }
-      {
-        const double L = v2 + 0.5 * s0, R = v3 - 0.5 * sp;
-        F1 = 0.5 * (L * fh[d][1].uL + R * fh[d][1].uR) - 0.5 * fh[d][1].a * (R - L);
-      }
+      const double F0 = species_face(v1 + 0.5 * sm, v2 - 0.5 * s0, fh[d][0]);
+      const double F1 = species_face(v2 + 0.5 * s0, v3 - 0.5 * sp, fh[d][1]);
       A -= (F1 - F0) * a.idx[d];
     }
     a.A[(i64)(SDC_NH + s) * a.Z + z] = A;
   }
-}
-
-// Rusanov flux of the hydro components through one face from the two
-// reconstructed states, plus the face data the species fluxes need.
-__device__ __forceinline__ void hydro_face(const double* WL, const double* WR, int d, double gamma, double alpha,
-                                           double* F, FaceHydro& fh) {
-  double FL[SDC_NH], FR[SDC_NH], pL, pR, cL, cR;
-  hydro_flux(WL, d, gamma, FL, fh.uL, pL, cL);
-  hydro_flux(WR, d, gamma, FR, fh.uR, pR, cR);
-  fh.a = alpha > 0.0 ? alpha : fmax(fabs(fh.uL) + cL, fabs(fh.uR) + cR);
-#pragma unroll
-  for (int q = 0; q < SDC_NH; ++q) F[q] = 0.5 * (FL[q] + FR[q]) - 0.5 * fh.a * (WR[q] - WL[q]);
-}
-
-__device__ __forceinline__ double species_face(double L, double R, const FaceHydro& f) {
-  return 0.5 * (L * f.uL + R * f.uR) - 0.5 * f.a * (R - L);
 }
 
 #if SDC_DIM == 3

@@ -392,6 +392,7 @@ struct sdc_handle_s {
   int32_t* d_blk_box = nullptr;
   RowDesc* d_rows = nullptr;  // row advection kernel: one descriptor per block
   int64_t n_rows = 0;
+  int zchunk = 0;  // row kernel tile: planes per z chunk (0: heuristic)
   hipStream_t last_stream = nullptr;
   std::string err;
   // per-kernel timing
@@ -551,18 +552,23 @@ int reset_queue(sdc_handle h, hipStream_t s) {
 
 // Blocks of the row advection kernel: every periodic grid (the domain, or
 // each box) is cut into slots (x-row y, z chunk), R = 256 / n0 slots per
-// block.  The chunk length is halved until the grid fills its blocks (boxes)
-// or the domain gives at least 2048 blocks, down to 2 (4) planes.
-std::vector<RowDesc> row_descriptors(const Prepared& P) {
+// block.  zmax = 0: the chunk starts at 32 planes and is halved until the
+// domain gives at least 2048 blocks (down to 4 planes); zmax > 0 (a tuned
+// tile): chunks of min(zmax, n2) planes.  A box's chunk is then halved until
+// its slots fill a block (down to 2 planes).
+std::vector<RowDesc> row_descriptors(const Prepared& P, int zmax) {
   std::vector<RowDesc> out;
   auto add_grid = [&](int64_t base, int n0, int n1, int n2, bool domain) {
     const int R = kBlock / n0;
-    int zc = n2 < 32 ? n2 : 32;
+    const int z0 = zmax > 0 ? zmax : 32;
+    int zc = n2 < z0 ? n2 : z0;
     auto slots = [&](int z) { return (int64_t)n1 * ((n2 + z - 1) / z); };
-    if (domain)
-      while (zc > 4 && (slots(zc) + R - 1) / R < 2048) zc = (zc + 1) / 2;
-    else
+    if (domain) {
+      if (zmax == 0)
+        while (zc > 4 && (slots(zc) + R - 1) / R < 2048) zc = (zc + 1) / 2;
+    } else {
       while (zc > 2 && slots(zc) < R) zc = (zc + 1) / 2;
+    }
     const int64_t ns = slots(zc);
     for (int64_t s0 = 0; s0 < ns; s0 += R) {
       RowDesc d;
@@ -596,6 +602,21 @@ bool rows_kernel_fits(const Prepared& P) {
     return true;
   }
   return c.n[0] <= kBlock;
+}
+
+// (Re)build the row descriptors for the current tile.
+int upload_rows(sdc_handle h) {
+  if (!h->f_advect_rows) return SDC_OK;
+  const std::vector<RowDesc> rows = row_descriptors(h->P, h->zchunk);
+  if (h->d_rows && (int64_t)rows.size() > h->n_rows) {
+    (void)hipFree(h->d_rows);
+    h->d_rows = nullptr;
+  }
+  if (!h->d_rows && hipMalloc((void**)&h->d_rows, rows.size() * sizeof(RowDesc)) != hipSuccess)
+    return fail(h, SDC_ERR_NOMEM, "hipMalloc(row descriptors) failed");
+  HIP_CHECK(h, hipMemcpy(h->d_rows, rows.data(), rows.size() * sizeof(RowDesc), hipMemcpyHostToDevice));
+  h->n_rows = (int64_t)rows.size();
+  return SDC_OK;
 }
 
 int advect(sdc_handle h, const double* U, double* A, hipStream_t s) {
@@ -936,18 +957,23 @@ int step_adjoint(sdc_handle h, double dt, const double* Un, const double* Ubar1,
 std::string tune_path(const sdc_handle h) {
   const sdc_config& c = h->P.cfg;
   char name[128];
-  std::snprintf(name, sizeof name, "tune3_%016llx_z%lld_k%d_a%d.txt", (unsigned long long)fnv1a(h->P.source),
+  std::snprintf(name, sizeof name, "tune4_%016llx_z%lld_k%d_a%d.txt", (unsigned long long)fnv1a(h->P.source),
                 (long long)h->P.Z, (int)c.n_iters, (int)c.advection);
   return cache_dir() + "/" + name;
 }
 
 bool load_tuning(sdc_handle h) {
   std::ifstream f(tune_path(h));
-  int o = -1, c = -1, sp = -1;
-  if (!(f >> o >> c >> sp) || o < 0 || o > 1 || c < 0 || sp < 0 || sp > 64) return false;
+  int o = -1, c = -1, sp = -1, zt = -1;
+  if (!(f >> o >> c >> sp >> zt) || o < 0 || o > 1 || c < 0 || sp < 0 || sp > 64 || zt < 0 || zt > 1024)
+    return false;
   h->occ2 = o;
   h->cap = c;
   h->split = sp;
+  if (zt != h->zchunk) {
+    h->zchunk = zt;
+    if (upload_rows(h) != SDC_OK) return false;
+  }
   h->tuned = true;
   return true;
 }
@@ -999,6 +1025,37 @@ int autotune(sdc_handle h, double dt, const double* U, const sdc_nodes& n, hipSt
           bs = sp;
         }
       }
+  // the advection tile: planes per z chunk of the row kernel, timed on A(U^n)
+  int bz = h->zchunk;
+  if (rc == SDC_OK && h->f_advect_rows) {
+    const int tiles[] = {0, 16, 32, 64, 128};
+    float bestz = 1e30f;
+    for (int rep = 0; rep < 2 && rc == SDC_OK; ++rep)
+      for (int zt : tiles) {
+        h->zchunk = zt;
+        if ((rc = upload_rows(h))) break;
+        if (hipEventRecord(e0, s) != hipSuccess) {
+          rc = fail(h, SDC_ERR_HIP, "autotune event failed");
+          break;
+        }
+        for (int i = 0; i < 3 && rc == SDC_OK; ++i) rc = advect(h, n.U[0], n.A[0], s);
+        if (rc) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          rc = fail(h, SDC_ERR_HIP, "autotune event failed");
+          break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep == 1 && ms < (zt == 0 ? bestz : 0.99f * bestz)) {
+          bestz = ms;
+          bz = zt;
+        }
+      }
+    if (rc == SDC_OK && bz != h->zchunk) {
+      h->zchunk = bz;
+      rc = upload_rows(h);
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   h->profile = prof;
@@ -1010,7 +1067,8 @@ int autotune(sdc_handle h, double dt, const double* U, const sdc_nodes& n, hipSt
   drop_graphs(h);
   HIP_CHECK(h, hipMemcpy(h->d_stats, saved, sizeof saved, hipMemcpyHostToDevice));
   const std::string path = tune_path(h);
-  std::string text = std::to_string(bo) + " " + std::to_string(bc) + " " + std::to_string(bs) + "\n";
+  std::string text = std::to_string(bo) + " " + std::to_string(bc) + " " + std::to_string(bs) + " " +
+                     std::to_string(bz) + "\n";
   std::vector<char> data(text.begin(), text.end());
   const auto k = path.rfind('/');
   write_file_atomic(path.substr(0, k), path.substr(k + 1), data);
@@ -1136,12 +1194,7 @@ int sdc_init(const sdc_config* cfg, const sdc_network* net, sdc_handle* out) {
     const char* name = h->P.cfg.slope == 0 ? "sdc_advect_rows_c" : "sdc_advect_rows";
     e = hipModuleGetFunction(&h->f_advect_rows, h->mod, name);
     if (e != hipSuccess) return bail(SDC_ERR_HIP, std::string("missing kernel ") + name);
-    const std::vector<RowDesc> rows = row_descriptors(h->P);
-    h->n_rows = (int64_t)rows.size();
-    if (hipMalloc((void**)&h->d_rows, rows.size() * sizeof(RowDesc)) != hipSuccess)
-      return bail(SDC_ERR_NOMEM, "hipMalloc(row descriptors) failed");
-    if (hipMemcpy(h->d_rows, rows.data(), rows.size() * sizeof(RowDesc), hipMemcpyHostToDevice) != hipSuccess)
-      return bail(SDC_ERR_HIP, "hipMemcpy(row descriptors) failed");
+    if (upload_rows(h) != SDC_OK) return bail(SDC_ERR_NOMEM, "row descriptors: " + h->err);
   }
   const std::vector<double> img = params_image(h->P, h->nra);
   e = hipMalloc(&h->d_params, img.size() * sizeof(double));
@@ -1343,10 +1396,15 @@ int sdc_step_adjoint(sdc_handle h, double dt, const double* U_n, const double* U
   return step_adjoint(h, dt, U_n, Ubar_np1, Ubar_n, thetabar, s);
 }
 
-int sdc_set_schedule(sdc_handle h, int32_t occ2, int32_t cap, int32_t split) {
+int sdc_set_schedule(sdc_handle h, int32_t occ2, int32_t cap, int32_t split, int32_t zchunk) {
   if (int rc = check_handle(h)) return rc;
-  if (occ2 < 0 || occ2 > 1 || cap < 0 || split < 0 || split > 64)
-    return fail(h, SDC_ERR_ARG, "occ2 must be 0 or 1, cap >= 0 and 0 <= split <= 64");
+  if (occ2 < 0 || occ2 > 1 || cap < 0 || split < 0 || split > 64 || zchunk < 0 || zchunk > 1024)
+    return fail(h, SDC_ERR_ARG, "occ2 must be 0 or 1, cap >= 0, 0 <= split <= 64 and 0 <= zchunk <= 1024");
+  if (zchunk != h->zchunk) {
+    if (h->last_stream) HIP_CHECK(h, hipStreamSynchronize(h->last_stream));  // descriptors in use
+    h->zchunk = zchunk;
+    if (int rc = upload_rows(h)) return rc;
+  }
   h->occ2 = occ2;
   h->cap = cap;
   h->split = split;
@@ -1355,11 +1413,12 @@ int sdc_set_schedule(sdc_handle h, int32_t occ2, int32_t cap, int32_t split) {
   return SDC_OK;
 }
 
-int sdc_get_schedule(sdc_handle h, int32_t* occ2, int32_t* cap, int32_t* split) {
+int sdc_get_schedule(sdc_handle h, int32_t* occ2, int32_t* cap, int32_t* split, int32_t* zchunk) {
   if (int rc = check_handle(h)) return rc;
   if (occ2) *occ2 = h->occ2;
   if (cap) *cap = h->cap;
   if (split) *split = h->split;
+  if (zchunk) *zchunk = h->zchunk;
   return SDC_OK;
 }
 

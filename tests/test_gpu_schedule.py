@@ -14,7 +14,8 @@ from tests.test_gpu_parity import make
 
 pytestmark = pytest.mark.gpu
 
-SCHEDULES = [(1, 0, 0), (0, 1, 0), (1, 2, 0), (0, 3, 0), (1, 4, 0), (0, 6, 0), (0, 0, 8), (1, 0, 3), (0, 2, 5)]
+SCHEDULES = [(1, 0, 0, 0), (0, 1, 0, 0), (1, 2, 0, 0), (0, 3, 0, 0), (1, 4, 0, 0), (0, 6, 0, 0), (0, 0, 8, 0),
+             (1, 0, 3, 0), (0, 2, 5, 0), (0, 0, 0, 2), (0, 0, 0, 5), (0, 0, 0, 64)]
 
 
 def one_step(h, w, nsteps=1):
@@ -30,13 +31,13 @@ def one_step(h, w, nsteps=1):
 def test_step_schedules_bitwise_identical(name, precision):
     w, prob, h = make(name, precision=precision)
     ref, sref = one_step(h, w, 2)
-    for occ2, cap, split in SCHEDULES:
-        h.set_schedule(occ2, cap, split)
-        assert h.schedule() == (occ2, cap, split)
+    for sched in SCHEDULES:
+        h.set_schedule(*sched)
+        assert h.schedule() == sched
         U, s = one_step(h, w, 2)
-        print(f"{name} p{precision} occ2={occ2} cap={cap} split={split}: identical={bool((U == ref).all())}")
-        assert bool((U == ref).all()), (occ2, cap, split)
-        assert s == sref, (occ2, cap, split)
+        print(f"{name} p{precision} schedule {sched}: identical={bool((U == ref).all())}")
+        assert bool((U == ref).all()), sched
+        assert s == sref, sched
 
 
 @pytest.mark.parametrize("cap", [1, 2, 5])
@@ -127,22 +128,25 @@ def test_bad_schedule_raises():
         h.set_schedule(0, -1)
     with pytest.raises(SDCError):
         h.set_schedule(0, 0, 65)
+    with pytest.raises(SDCError):
+        h.set_schedule(0, 0, 0, -1)
 
 
-def test_autotune_keeps_results_and_stats():
-    w, prob, h = make("net2d")
+@pytest.mark.parametrize("name", ["net2d", "net3d"])
+def test_autotune_keeps_results_and_stats(name):
+    w, prob, h = make(name)
     ref, sref = one_step(h, w)
     nc = w["U0"].shape[0]
     U = to_gpu(w["U0"].reshape(nc, -1))
     h.stats_reset()
-    occ2, cap, split = h.autotune(w["dt"], U)
-    print(f"autotuned schedule: occ2={occ2} cap={cap} split={split}")
-    assert occ2 in (0, 1) and cap in (0, 4, 5, 6) and split == 0
+    occ2, cap, split, zchunk = h.autotune(w["dt"], U)
+    print(f"autotuned schedule: occ2={occ2} cap={cap} split={split} zchunk={zchunk}")
+    assert occ2 in (0, 1) and cap in (0, 4, 5, 6) and split == 0 and zchunk in (0, 16, 32, 64, 128)
     assert h.stats()["solves"] == 0
     assert bool((U == to_gpu(w["U0"].reshape(nc, -1))).all())  # input untouched
     U2, s2 = one_step(h, w)
     assert bool((U2 == ref).all()) and s2 == sref
-    _, _, ha = make("net2d", autotune=1)  # tunes on its first step (or reads the cached choice)
+    _, _, ha = make(name, autotune=1)  # tunes on its first step (or reads the cached choice)
     U3, s3 = one_step(ha, w)
     assert bool((U3 == ref).all()) and s3 == sref
     assert ha.schedule()[0] in (0, 1)
