@@ -106,12 +106,14 @@ def recorded_traffic(h, kernel):
     return float(rec["traffic_bytes_per_launch"]), digest
 
 
-def make_handle(w, precision, schedule):
-    """'auto': the handle tunes its Newton schedule on its first step (or reads
-    the choice cached on disk for this kernel source and size); 'O,C': fixed
-    occupancy variant and iteration cap."""
+def make_handle(w, precision, schedule, graph=0):
+    """'auto': the handle tunes its schedule on its first step (or reads the
+    choice cached on disk for this kernel source and size); otherwise the
+    comma-separated schedule (occupancy variant, iteration cap, split batches,
+    advection tile).  graph=1: every step replays a captured HIP graph."""
     from paper_1910_12578_amd import SDC, config_from_workload
-    h = SDC(config_from_workload(w, precision=precision, autotune=int(schedule == "auto")), w["network"])
+    h = SDC(config_from_workload(w, precision=precision, autotune=int(schedule == "auto"), graph=graph),
+            w["network"])
     if schedule != "auto":
         vals = [int(v) for v in schedule.split(",")]
         h.set_schedule(*vals)
@@ -227,27 +229,33 @@ def run_adjoint_ratio(nsteps=20):
 
 
 def run_boxes(steps, warmup, precision, schedule="auto"):
-    """Batched boxes: 4096 periodic boxes, edges in {8,16,32,64}, one launch per kernel."""
+    """Batched boxes: 4096 periodic boxes, edges in {8,16,32,64}, one launch
+    per kernel over all boxes; then the same steps replayed from captured HIP
+    graphs (one per buffer-rotation phase of a step)."""
     import torch
     w = si.boxes_workload()
-    h = make_handle(w, precision, schedule)
-    U = torch.from_numpy(w["U0"]).to("cuda")
-    work = h.alloc_nodes()
-    sched = warm(h, w["dt"], U, work, warmup, schedule)
-    h.stats_reset()
-    t0 = time.perf_counter()
-    h.step(w["dt"], steps, U, work)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    st = h.stats()
     Z = w["U0"].shape[1]
-    out = dict(workload=f"{len(w['box_n'])} boxes, edges in {{8,16,32,64}}, {Z} zones, 0.2 CFL step",
-               zone_updates=Z * steps / el, ms_per_step=1e3 * el / steps,
-               mean_newton=st["iters"] / max(st["solves"] - st["failed"], 1), failed=st["failed"],
-               newton_hist={i: v for i, v in enumerate(st["hist"]) if v}, schedule=sched)
-    h.close()
-    del U, work
-    torch.cuda.empty_cache()
+    out = dict(workload=f"{len(w['box_n'])} boxes, edges in {{8,16,32,64}}, {Z} zones, 0.2 CFL step")
+    for graph in (0, 1):
+        h = make_handle(w, precision, schedule, graph=graph)
+        U = torch.from_numpy(w["U0"]).to("cuda")
+        work = h.alloc_nodes()
+        sched = warm(h, w["dt"], U, work, max(warmup, 1) if graph else warmup, schedule)
+        h.stats_reset()
+        t0 = time.perf_counter()
+        h.step(w["dt"], steps, U, work)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st = h.stats()
+        if graph:
+            out["graph"] = dict(zone_updates=Z * steps / el, ms_per_step=1e3 * el / steps)
+        else:
+            out.update(zone_updates=Z * steps / el, ms_per_step=1e3 * el / steps,
+                       mean_newton=st["iters"] / max(st["solves"] - st["failed"], 1), failed=st["failed"],
+                       newton_hist={i: v for i, v in enumerate(st["hist"]) if v}, schedule=sched)
+        h.close()
+        del U, work
+        torch.cuda.empty_cache()
     return out
 
 
