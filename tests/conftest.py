@@ -8,4 +8,4 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP path)")
-    config.addinivalue_line("markers", "slow: long CPU-only oracle check")
+    config.addinivalue_line("markers", "slow: long check (tens of seconds to minutes)")
