@@ -292,6 +292,15 @@ int sdc_cost_model(sdc_handle h, int64_t* out);
  */
 int sdc_compile_only(const sdc_config* cfg, const sdc_network* net);
 
+/* Path of the ahead-of-time code object for `cfg` and `net` in the kernel
+ * cache directory (SDC_KERNEL_CACHE, else _kcache beside the library).  A
+ * build step may place there the generated source compiled with hipcc
+ * --genco and the options of the run-time compiler; sdc_init then loads it
+ * instead of compiling with hipRTC.  Copies up to `len` bytes including the
+ * terminator into `buf` and returns the full length needed, or a negative
+ * SDC_ERR_* code. */
+int64_t sdc_aot_name(const sdc_config* cfg, const sdc_network* net, char* buf, int64_t len);
+
 /* Generated device source for `cfg` and `net` (for inspection): copies up to
  * `len` bytes including the terminator into `buf` and returns the full length
  * needed, or a negative SDC_ERR_* code. */

@@ -23,7 +23,7 @@ ERRORS = {1: "SDC_ERR_ARG", 2: "SDC_ERR_HIP", 3: "SDC_ERR_NOMEM", 4: "SDC_ERR_NE
 EXPORTS = ("sdc_config_default", "sdc_init", "sdc_destroy", "sdc_last_error", "sdc_sizes",
            "sdc_advective_term", "sdc_source", "sdc_reaction_solve", "sdc_sweep", "sdc_step",
            "sdc_stats", "sdc_stats_reset", "sdc_set_params", "sdc_compile_only",
-           "sdc_generated_source", "sdc_profile_enable", "sdc_profile_read", "sdc_cost_model",
+           "sdc_generated_source", "sdc_aot_name", "sdc_profile_enable", "sdc_profile_read", "sdc_cost_model",
            "sdc_step_adjoint", "sdc_set_schedule", "sdc_get_schedule", "sdc_autotune")
 KINDS = ("advect", "source", "solve", "transition_first", "transition_node0", "transition_later", "fill",
          "adjoint", "finish", "split")
@@ -86,6 +86,8 @@ def lib():
         L.sdc_compile_only.argtypes = [POINTER(Config), POINTER(Network)]
         L.sdc_generated_source.argtypes = [POINTER(Config), POINTER(Network), c_char_p, c_int64]
         L.sdc_generated_source.restype = c_int64
+        L.sdc_aot_name.argtypes = [POINTER(Config), POINTER(Network), c_char_p, c_int64]
+        L.sdc_aot_name.restype = c_int64
         L.sdc_profile_enable.argtypes = [c_void_p, c_int32]
         L.sdc_profile_read.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int64)]
         L.sdc_cost_model.argtypes = [c_void_p, POINTER(c_int64)]
@@ -168,6 +170,19 @@ def generated_source(cfg, net):
         _check(-need)
     buf = ctypes.create_string_buffer(int(need))
     lib().sdc_generated_source(byref(c), byref(n), buf, need)
+    return buf.value.decode()
+
+
+def aot_name(cfg, net):
+    """Path at which the runtime looks for the hipcc-built code object of
+    `cfg` and `net` before compiling with hipRTC."""
+    c = make_config(cfg)
+    n, _keep = make_network(net)
+    need = lib().sdc_aot_name(byref(c), byref(n), None, 0)
+    if need < 0:
+        _check(-need)
+    buf = ctypes.create_string_buffer(int(need))
+    lib().sdc_aot_name(byref(c), byref(n), buf, need)
     return buf.value.decode()
 
 

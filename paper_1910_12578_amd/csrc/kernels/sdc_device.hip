@@ -589,12 +589,6 @@ __device__ __forceinline__ int newton_fast(double* x, double* b, double irho, do
   __shared__ double sh_x[SDC_NX][256], sh_b[SDC_NX][256];
   const LdsVec xs{(__attribute__((address_space(3))) double*)&sh_x[0][threadIdx.x]};
   const LdsVec bs{(__attribute__((address_space(3))) double*)&sh_b[0][threadIdx.x]};
-#ifndef SDC_MIXED
-  __shared__ double sh_g[SDC_NX][256];
-  const LdsVec gs{(__attribute__((address_space(3))) double*)&sh_g[0][threadIdx.x]};
-#else
-  const LdsVec gs{nullptr};
-#endif
 #pragma unroll
   for (int i = 0; i < SDC_NX; ++i) {
     xs.set(i, x[i]);
@@ -609,27 +603,17 @@ __device__ __forceinline__ int newton_fast(double* x, double* b, double irho, do
     double G[SDC_NX];
     MT M[SDC_NNZ];
     net_residual_matrix<MT>(xs, bs, irho, dtm, P, gm1, G, M);
+    // the right-hand side rides along the factorisation, which drops each
+    // multiplier once it is applied (mixed mode: rounded to the matrix type)
     MT r[SDC_NX];
-    if constexpr (sizeof(MT) == sizeof(double)) {
-      // an FP64 matrix leaves no room for the residual during the factorisation
 #pragma unroll
-      for (int i = 0; i < SDC_NX; ++i) gs.set(i, G[i]);
-      asm volatile("" ::: "memory");
-    } else {
-      // the mixed mode carries the rounded right-hand side (half the registers)
+    for (int i = 0; i < SDC_NX; ++i) r[i] = (MT)(-G[i]);
+    // A failed pivot guard zeroes the step instead of leaving the loop here:
+    // a branch between the factorisation and the update splits them into
+    // separately scheduled blocks and costs about a hundred registers.
+    const bool ok = net_lu_solve<MT>(M, r, (MT)tau);
 #pragma unroll
-      for (int i = 0; i < SDC_NX; ++i) r[i] = (MT)(-G[i]);
-    }
-    if (!net_lu<MT>(M, (MT)tau)) {
-      st = 2;
-      break;
-    }
-    if constexpr (sizeof(MT) == sizeof(double)) {
-      asm volatile("" ::: "memory");
-#pragma unroll
-      for (int i = 0; i < SDC_NX; ++i) r[i] = (MT)(-gs.get(i));
-    }
-    net_solve<MT>(M, r);
+    for (int i = 0; i < SDC_NX; ++i) r[i] = ok ? r[i] : (MT)0;
     asm volatile("" ::: "memory");
     double err = 0.0, inf_or_nan = ise * 0.0;  // fmax drops NaN, so track it apart
 #pragma unroll
@@ -638,6 +622,10 @@ __device__ __forceinline__ int newton_fast(double* x, double* b, double irho, do
       xs.set(i, xs.get(i) + d);
       err = fmax(err, fabs(d) * (i == SDC_NX - 1 ? ise : irho));
       inf_or_nan += d * 0.0;
+    }
+    if (!ok) {  // x is unchanged: x + 0 == x
+      st = 2;
+      break;
     }
     if (!(inf_or_nan == 0.0)) {
       st = 3;

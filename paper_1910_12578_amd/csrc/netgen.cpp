@@ -325,18 +325,43 @@ std::string generate(const Topology& t, const Pattern& p) {
   }
   E << "  return ok;\n}\n\n";
 
-  // ---- forward / backward substitution: r <- M^{-1} r
-  E << "// Solve with the packed LU factors in place: r <- (LU)^{-1} r.\n";
-  E << "template <class MT>\n__device__ __forceinline__ void net_solve(const MT* M, MT* r) {\n";
-  for (int k = 0; k < n; ++k)
+  // ---- LU with the forward substitution folded in: each multiplier updates
+  // the right-hand side as soon as it is formed and is then dropped (only U
+  // stays live), followed by the backward substitution.  The operations on r
+  // are those of net_lu followed by net_solve, in the same order.
+  E << "// Factor and solve in one pass: r <- M^{-1} r; M keeps U (diagonal 1/pivot), not L.\n";
+  E << "template <class MT>\n__device__ __forceinline__ bool net_lu_solve(MT* M, MT* r, MT tau) {\n  bool ok = true;\n";
+  for (int k = 0; k < n; ++k) {
+    int dk = p.index[k * n + k];
+    std::vector<int> rows, cols;
     for (int i = k + 1; i < n; ++i)
-      if (p.index[i * n + k] >= 0) E << "  r[" << i << "] = fma(-M[" << p.index[i * n + k] << "], r[" << k << "], r[" << i << "]);\n";
+      if (p.index[i * n + k] >= 0) rows.push_back(i);
+    for (int j = k + 1; j < n; ++j)
+      if (p.index[k * n + j] >= 0) cols.push_back(j);
+    E << "  {\n    const MT piv = M[" << dk << "];\n";
+    if (!rows.empty()) {
+      E << "    MT cmax = fabs(piv);\n";
+      for (int i : rows) E << "    cmax = fmax(cmax, fabs(M[" << p.index[i * n + k] << "]));\n";
+      E << "    ok = ok && (fabs(piv) >= tau * cmax);\n";
+    } else {
+      E << "    ok = ok && (fabs(piv) >= tau * fabs(piv)) && (piv != (MT)0);\n";
+    }
+    E << "    const MT inv = net_rcp(piv);\n    M[" << dk << "] = inv;\n";
+    for (int i : rows) {
+      int li = p.index[i * n + k];
+      E << "    { const MT l = M[" << li << "] * inv;\n";
+      E << "      r[" << i << "] = fma(-l, r[" << k << "], r[" << i << "]);\n";
+      for (int j : cols) E << "      M[" << p.index[i * n + j] << "] = fma(-l, M[" << p.index[k * n + j] << "], M[" << p.index[i * n + j] << "]);\n";
+      E << "    }\n";
+    }
+    E << "  }\n";
+  }
   for (int k = n - 1; k >= 0; --k) {
     for (int j = k + 1; j < n; ++j)
       if (p.index[k * n + j] >= 0) E << "  r[" << k << "] = fma(-M[" << p.index[k * n + j] << "], r[" << j << "], r[" << k << "]);\n";
     E << "  r[" << k << "] *= M[" << p.index[k * n + k] << "];\n";
   }
-  E << "}\n\n";
+  E << "  return ok;\n}\n\n";
 
   // ---- transpose solve: r <- (LU)^{-T} r  (adjoint of the implicit solve)
   E << "// Solve with the transposed factors: r <- (LU)^{-T} r.\n";

@@ -134,7 +134,20 @@ void write_file_atomic(const std::string& dir, const std::string& name, const st
   std::rename(tmp.c_str(), (dir + "/" + name).c_str());
 }
 
-// Code object for `src`: in-process cache, then the on-disk cache, then hipRTC.
+// Name of the ahead-of-time code object of `src` (compiled with hipcc at build
+// time): keyed by the source and the options only.
+std::string aot_name(const std::string& src) {
+  std::string key_text = src;
+  for (const char* o : compile_options()) key_text += std::string("\n//opt ") + o;
+  char name[64];
+  std::snprintf(name, sizeof name, "sdc_%016llx.aot.co", (unsigned long long)fnv1a(key_text));
+  return name;
+}
+
+// Code object for `src`: in-process cache, then the ahead-of-time object of
+// the build step, then the on-disk cache of run-time compilations, then
+// hipRTC.  The run-time key includes the hipRTC version, which depends on the
+// process (a hipRTC library loaded earlier by another component wins).
 int get_code_object(const std::string& src, std::vector<char>* code, std::string* err) {
   std::string key_text = src;
   for (const char* o : compile_options()) key_text += std::string("\n//opt ") + o;
@@ -153,7 +166,7 @@ int get_code_object(const std::string& src, std::vector<char>* code, std::string
     }
   }
   const std::string dir = cache_dir();
-  if (read_file(dir + "/" + name, code)) {
+  if (read_file(dir + "/" + aot_name(src), code) || read_file(dir + "/" + name, code)) {
     std::lock_guard<std::mutex> lk(g_cache_mutex);
     g_code_cache[key] = *code;
     return SDC_OK;
@@ -1120,6 +1133,24 @@ int64_t sdc_generated_source(const sdc_config* cfg, const sdc_network* net, char
   if (buf && len > 0) {
     const int64_t n = need < len ? need : len;
     std::memcpy(buf, P.source.c_str(), (size_t)n - 1);
+    buf[n - 1] = '\0';
+  }
+  return need;
+}
+
+int64_t sdc_aot_name(const sdc_config* cfg, const sdc_network* net, char* buf, int64_t len) {
+  Prepared P;
+  std::string err;
+  int rc = prepare(cfg, net, &P, &err);
+  if (rc) {
+    g_init_error = err;
+    return -rc;
+  }
+  const std::string name = cache_dir() + "/" + aot_name(P.source);
+  const int64_t need = (int64_t)name.size() + 1;
+  if (buf && len > 0) {
+    const int64_t n = need < len ? need : len;
+    std::memcpy(buf, name.c_str(), (size_t)n - 1);
     buf[n - 1] = '\0';
   }
   return need;
