@@ -251,8 +251,10 @@ __device__ __forceinline__ double ld_at(__amdgpu_buffer_rsrc_t r, unsigned voff,
 
 typedef unsigned u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
 
+// Non-temporal (cache policy nt): the output is not read again in this
+// launch and should not evict the neighbour rows that are.
 __device__ __forceinline__ void st_at(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 2);
 }
 
 __device__ __forceinline__ int wrap_index(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
@@ -832,6 +834,12 @@ __device__ __forceinline__ constexpr int react_index(int c) {
   return c == 1 + SDC_DIM ? SDC_NX - 1 : (c >= SDC_NH ? c - SDC_NH : -1);
 }
 
+// Streaming accesses of the transition kernels: every value is read or
+// written once per launch, so they are marked non-temporal and leave the
+// caches to what is reused (the Newton kernels' register spill).
+__device__ __forceinline__ double ld_s(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void st_s(double* p, double v) { __builtin_nontemporal_store(v, p); }
+
 // Finalise node m+1 of zone z: rho, rho u from the explicit part, rho E =
 // x_e + KE, rho X = x_s, and R^{m+1} re-evaluated at the root.
 // (FULL = false: rho and rho u were written by the explicit-part kernel.)
@@ -843,15 +851,15 @@ __device__ __forceinline__ void transition_store(const TransArgs& a, i64 z, doub
   net_source(x, 1.0 / rho, P, a.gm1, R);
   double* __restrict__ Uo = a.Uout;
   if (FULL) {
-    Uo[z] = rho;
+    st_s(&Uo[z], rho);
 #pragma unroll
-    for (int d = 0; d < SDC_DIM; ++d) Uo[(i64)(1 + d) * Z + z] = mom[d];
+    for (int d = 0; d < SDC_DIM; ++d) st_s(&Uo[(i64)(1 + d) * Z + z], mom[d]);
   }
-  Uo[(i64)(1 + SDC_DIM) * Z + z] = x[SDC_NX - 1] + ke;
+  st_s(&Uo[(i64)(1 + SDC_DIM) * Z + z], x[SDC_NX - 1] + ke);
 #pragma unroll
-  for (int s = 0; s < SDC_NS; ++s) Uo[(i64)(SDC_NH + s) * Z + z] = x[s];
+  for (int s = 0; s < SDC_NS; ++s) st_s(&Uo[(i64)(SDC_NH + s) * Z + z], x[s]);
 #pragma unroll
-  for (int i = 0; i < SDC_NX; ++i) a.Rout[(i64)i * Z + z] = R[i];
+  for (int i = 0; i < SDC_NX; ++i) st_s(&a.Rout[(i64)i * Z + z], R[i]);
 }
 
 // Explicit part of the transition of zone z: the right-hand side of Eq. 2
@@ -866,7 +874,7 @@ __device__ __forceinline__ void transition_explicit(const TransArgs& a, i64 z, d
     double rhs[SDC_NC];
     if (KIND == KIND_FIRST) {
 #pragma unroll
-      for (int c = 0; c < SDC_NC; ++c) rhs[c] = fma(a.dtm, a.Am[(i64)c * Z + z], a.Um[(i64)c * Z + z]);
+      for (int c = 0; c < SDC_NC; ++c) rhs[c] = fma(a.dtm, ld_s(&a.Am[(i64)c * Z + z]), ld_s(&a.Um[(i64)c * Z + z]));
     } else if (KIND == KIND_NODE0) {
 #pragma unroll
       for (int c = 0; c < SDC_NC; ++c) {
@@ -874,29 +882,29 @@ __device__ __forceinline__ void transition_explicit(const TransArgs& a, i64 z, d
         double f[SDC_NNODES];
 #pragma unroll
         for (int j = 0; j <= SDC_M; ++j) {
-          f[j] = a.Aold[j][(i64)c * Z + z];
-          if (ri >= 0) f[j] += a.Rold[j][(i64)ri * Z + z];
+          f[j] = ld_s(&a.Aold[j][(i64)c * Z + z]);
+          if (ri >= 0) f[j] += ld_s(&a.Rold[j][(i64)ri * Z + z]);
         }
         double i0 = 0.0;
 #pragma unroll
         for (int j = 0; j <= SDC_M; ++j) i0 = fma(a.S[0][j], f[j], i0);
-        double r = fma(a.dt, i0, a.Um[(i64)c * Z + z]);
-        if (ri >= 0) r = fma(-a.dtm, a.Rold[1][(i64)ri * Z + z], r);
+        double r = fma(a.dt, i0, ld_s(&a.Um[(i64)c * Z + z]));
+        if (ri >= 0) r = fma(-a.dtm, ld_s(&a.Rold[1][(i64)ri * Z + z]), r);
         rhs[c] = r;
 #pragma unroll
         for (int mm = 1; mm < SDC_M; ++mm) {
           double im = 0.0;
 #pragma unroll
           for (int j = 0; j <= SDC_M; ++j) im = fma(a.S[mm][j], f[j], im);
-          double cm = fma(-a.dtj[mm], a.Aold[mm][(i64)c * Z + z], a.dt * im);
-          if (ri >= 0) cm = fma(-a.dtj[mm], a.Rold[mm + 1][(i64)ri * Z + z], cm);
-          a.Cout[mm - 1][(i64)c * Z + z] = cm;
+          double cm = fma(-a.dtj[mm], ld_s(&a.Aold[mm][(i64)c * Z + z]), a.dt * im);
+          if (ri >= 0) cm = fma(-a.dtj[mm], ld_s(&a.Rold[mm + 1][(i64)ri * Z + z]), cm);
+          st_s(&a.Cout[mm - 1][(i64)c * Z + z], cm);
         }
       }
     } else {
 #pragma unroll
       for (int c = 0; c < SDC_NC; ++c)
-        rhs[c] = fma(a.dtm, a.Am[(i64)c * Z + z], a.Um[(i64)c * Z + z]) + a.Cin[(i64)c * Z + z];
+        rhs[c] = fma(a.dtm, ld_s(&a.Am[(i64)c * Z + z]), ld_s(&a.Um[(i64)c * Z + z])) + ld_s(&a.Cin[(i64)c * Z + z]);
     }
     // explicit part: rho and rho u are final
     rho = rhs[0];
@@ -913,15 +921,15 @@ __device__ __forceinline__ void transition_explicit(const TransArgs& a, i64 z, d
     // energy part of the Newton guess: previous iterate of node m+1
     {
       const double* __restrict__ g = a.guess;
-      const double grho = g[z];
+      const double grho = ld_s(&g[z]);
       double gke = 0.0;
 #pragma unroll
       for (int d = 0; d < SDC_DIM; ++d) {
-        const double mo = g[(i64)(1 + d) * Z + z];
+        const double mo = ld_s(&g[(i64)(1 + d) * Z + z]);
         gke = fma(mo, mo, gke);
       }
       gke = 0.5 * gke / grho;
-      xe_guess = g[(i64)(1 + SDC_DIM) * Z + z] - gke;
+      xe_guess = ld_s(&g[(i64)(1 + SDC_DIM) * Z + z]) - gke;
     }
   }
 }
@@ -939,7 +947,7 @@ __device__ __forceinline__ void transition_body(const TransArgs& a) {
     transition_explicit<KIND>(a, z, rho, ke, mom, b, x[SDC_NX - 1]);
     // species part of the Newton guess
 #pragma unroll
-    for (int s = 0; s < SDC_NS; ++s) x[s] = a.guess[(i64)(SDC_NH + s) * Z + z];
+    for (int s = 0; s < SDC_NS; ++s) x[s] = ld_s(&a.guess[(i64)(SDC_NH + s) * Z + z]);
     it = newton_fast<MT>(x, b, 1.0 / rho, 1.0 / fabs(b[SDC_NX - 1]), a.dtm, P, a.gm1, a.ctl.tol, a.ctl.tau, 1,
                          min(a.ctl.cap, a.ctl.maxiter), st);
   }
