@@ -944,10 +944,15 @@ __device__ __forceinline__ void transition_body(const TransArgs& a) {
   double b[SDC_NX], x[SDC_NX];
   int it = 0, st = 3;
   if (valid) {
+    // the m = 0 prologue (the quadrature inputs of every node) issues its
+    // loads ahead of the other wave's Newton work (measured: helps the m = 0
+    // transition, slows the lighter ones)
+    if (KIND == KIND_NODE0) __builtin_amdgcn_s_setprio(2);
     transition_explicit<KIND>(a, z, rho, ke, mom, b, x[SDC_NX - 1]);
     // species part of the Newton guess
 #pragma unroll
     for (int s = 0; s < SDC_NS; ++s) x[s] = ld_s(&a.guess[(i64)(SDC_NH + s) * Z + z]);
+    if (KIND == KIND_NODE0) __builtin_amdgcn_s_setprio(0);
     it = newton_fast<MT>(x, b, 1.0 / rho, 1.0 / fabs(b[SDC_NX - 1]), a.dtm, P, a.gm1, a.ctl.tol, a.ctl.tau, 1,
                          min(a.ctl.cap, a.ctl.maxiter), st);
   }
