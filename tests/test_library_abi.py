@@ -124,3 +124,18 @@ def test_product_path_does_not_import_the_oracle():
             if f.endswith((".py", ".cpp", ".hip", ".h", ".hpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
+
+
+def test_ahead_of_time_kernels_of_the_standard_workloads(binding):
+    """build() compiles the standard workloads' kernels with hipcc into the
+    kernel cache under the name the runtime looks for first."""
+    names = set()
+    for name, shape in (("net2d", (8, 8)), ("net3d", (4, 4, 4))):
+        w = si.workload(name, shape=shape)
+        for prec in (0, 1):
+            path = binding.aot_name(binding.config_from_workload(w, precision=prec), w["network"])
+            assert path == binding.aot_name(binding.config_from_workload(w, precision=prec), w["network"])
+            assert path.endswith(".aot.co") and os.path.basename(os.path.dirname(path)) == "_kcache"
+            assert os.path.getsize(path) > 0, path
+            names.add(path)
+    assert len(names) == 4
