@@ -328,7 +328,8 @@ std::string generate(const Topology& t, const Pattern& p) {
   // ---- LU with the forward substitution folded in: each multiplier updates
   // the right-hand side as soon as it is formed and is then dropped (only U
   // stays live), followed by the backward substitution.  The operations on r
-  // are those of net_lu followed by net_solve, in the same order.
+  // are those of a forward substitution with the factors of net_lu (k
+  // ascending) and a backward one, in the same order.
   E << "// Factor and solve in one pass: r <- M^{-1} r; M keeps U (diagonal 1/pivot), not L.\n";
   E << "template <class MT>\n__device__ __forceinline__ bool net_lu_solve(MT* M, MT* r, MT tau) {\n  bool ok = true;\n";
   for (int k = 0; k < n; ++k) {

@@ -35,7 +35,7 @@ struct FlopCount {
   long source = 0;           // net_source: R(x)
   long residual_matrix = 0;  // net_residual_matrix: G and the Newton matrix
   long lu = 0;               // net_lu
-  long solve = 0;            // net_solve
+  long solve = 0;            // forward and backward substitution
   long exps = 0;             // exp calls per R or residual evaluation
 };
 
@@ -44,8 +44,8 @@ FlopCount count_flops(const Topology& t, const Pattern& p);
 Pattern build_pattern(const Topology& t);
 
 // Device source (C++ text) defining the network constants and functions
-//   net_source, net_residual_matrix<MT>, net_lu<MT>, net_solve<MT>,
-//   net_residual_dense, net_vjp_x, net_vjp_params  (see the generated comments).
+//   net_source, net_residual_matrix<MT>, net_lu_solve<MT>, net_lu<MT>, net_solve_t<MT>,
+//   net_residual_dense, net_vjp  (see the generated comments).
 std::string generate(const Topology& t, const Pattern& p);
 
 }  // namespace sdcgen
