@@ -746,33 +746,38 @@ __device__ __forceinline__ void reaction_solve_body(const SolveArgs& a) {
 
 template <class MT>
 __device__ __forceinline__ void reaction_finish_body(const SolveArgs& a) {
-  const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = i < (i64)*a.q.count;
   ParamPtr P = stage_params(a.P);
-  int nu = 0, fb = 0;
-  bool nonfinite = false;
-  if (valid) {
-    const i64 cap = a.q.capacity;
-    const i64 z = a.q.z[i];
-    double x[SDC_NX], b[SDC_NX];
+  // a bounded grid strides over the queue; the trip count is uniform per
+  // block (the barriers of stats_block)
+  const i64 count = (i64)*a.q.count, stride = (i64)gridDim.x * blockDim.x;
+  for (i64 base = (i64)blockIdx.x * blockDim.x; base < count; base += stride) {
+    const i64 i = base + threadIdx.x;
+    const bool valid = i < count;
+    int nu = 0, fb = 0;
+    bool nonfinite = false;
+    if (valid) {
+      const i64 cap = a.q.capacity;
+      const i64 z = a.q.z[i];
+      double x[SDC_NX], b[SDC_NX];
 #pragma unroll
-    for (int k = 0; k < SDC_NX; ++k) {
-      x[k] = a.q.x[(i64)k * cap + i];
-      b[k] = a.q.b[(i64)k * cap + i];
-    }
-    const double rho = a.q.aux[i];
-    nu = newton_finish<MT>(x, b, rho, a.dtm, P, a.gm1, a.ctl, a.q.it[i], fb);
-    double R[SDC_NX];
-    net_source(x, 1.0 / rho, P, a.gm1, R);
+      for (int k = 0; k < SDC_NX; ++k) {
+        x[k] = a.q.x[(i64)k * cap + i];
+        b[k] = a.q.b[(i64)k * cap + i];
+      }
+      const double rho = a.q.aux[i];
+      nu = newton_finish<MT>(x, b, rho, a.dtm, P, a.gm1, a.ctl, a.q.it[i], fb);
+      double R[SDC_NX];
+      net_source(x, 1.0 / rho, P, a.gm1, R);
 #pragma unroll
-    for (int k = 0; k < SDC_NX; ++k) {
-      a.x[(i64)k * a.Z + z] = x[k];
-      a.R[(i64)k * a.Z + z] = R[k];
+      for (int k = 0; k < SDC_NX; ++k) {
+        a.x[(i64)k * a.Z + z] = x[k];
+        a.R[(i64)k * a.Z + z] = R[k];
+      }
+      a.iters[z] = nu;
+      nonfinite = !all_finite(x);
     }
-    a.iters[z] = nu;
-    nonfinite = !all_finite(x);
+    stats_block(a.stats, nu, valid, nonfinite, fb);
   }
-  stats_block(a.stats, nu, valid, nonfinite, fb);
 }
 
 #ifndef SDC_MIXED
@@ -983,28 +988,33 @@ __device__ __forceinline__ void transition_body(const TransArgs& a) {
 
 template <class MT>
 __device__ __forceinline__ void transition_finish_body(const TransArgs& a) {
-  const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = i < (i64)*a.q.count;
   ParamPtr P = stage_params(a.P);
-  int nu = 0, fb = 0;
-  bool nonfinite = false;
-  if (valid) {
-    const i64 cap = a.q.capacity;
-    const i64 z = a.q.z[i];
-    double x[SDC_NX], b[SDC_NX], mom[SDC_DIM];
+  // a bounded grid strides over the queue; the trip count is uniform per
+  // block (the barriers of stats_block)
+  const i64 count = (i64)*a.q.count, stride = (i64)gridDim.x * blockDim.x;
+  for (i64 base = (i64)blockIdx.x * blockDim.x; base < count; base += stride) {
+    const i64 i = base + threadIdx.x;
+    const bool valid = i < count;
+    int nu = 0, fb = 0;
+    bool nonfinite = false;
+    if (valid) {
+      const i64 cap = a.q.capacity;
+      const i64 z = a.q.z[i];
+      double x[SDC_NX], b[SDC_NX], mom[SDC_DIM];
 #pragma unroll
-    for (int k = 0; k < SDC_NX; ++k) {
-      x[k] = a.q.x[(i64)k * cap + i];
-      b[k] = a.q.b[(i64)k * cap + i];
+      for (int k = 0; k < SDC_NX; ++k) {
+        x[k] = a.q.x[(i64)k * cap + i];
+        b[k] = a.q.b[(i64)k * cap + i];
+      }
+      const double rho = a.q.aux[i], ke = a.q.aux[cap + i];
+#pragma unroll
+      for (int d = 0; d < SDC_DIM; ++d) mom[d] = a.q.aux[(i64)(2 + d) * cap + i];
+      nu = newton_finish<MT>(x, b, rho, a.dtm, P, a.gm1, a.ctl, a.q.it[i], fb);
+      transition_store(a, z, rho, ke, mom, x, P);
+      nonfinite = !all_finite(x);
     }
-    const double rho = a.q.aux[i], ke = a.q.aux[cap + i];
-#pragma unroll
-    for (int d = 0; d < SDC_DIM; ++d) mom[d] = a.q.aux[(i64)(2 + d) * cap + i];
-    nu = newton_finish<MT>(x, b, rho, a.dtm, P, a.gm1, a.ctl, a.q.it[i], fb);
-    transition_store(a, z, rho, ke, mom, x, P);
-    nonfinite = !all_finite(x);
+    stats_block(a.stats, nu, valid, nonfinite, fb);
   }
-  stats_block(a.stats, nu, valid, nonfinite, fb);
 }
 
 // ---- split schedule.  The explicit part (quadrature, rhs, final rho and

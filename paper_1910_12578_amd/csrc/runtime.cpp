@@ -33,6 +33,9 @@ namespace {
 thread_local std::string g_init_error;
 
 constexpr int kBlock = 256;
+// Grid of the deferred-zone finish kernels, which stride over the queue: an
+// empty queue then costs a few microseconds instead of a launch over all zones.
+constexpr int64_t kFinishThreads = 2048 * kBlock;
 
 // ------------------------------------------------------------ quadrature
 // Gauss-Lobatto points on [0, 1] for 2..5 nodes (closed forms).
@@ -709,7 +712,7 @@ int split_transition(sdc_handle h, int kind, TransArgs a, hipStream_t s) {
     if (int rc = launch(h, fn, a.zcount, &a, s)) return rc;
   }
   h->profile = false;  // the finish kernel is part of the span
-  int rc = launch(h, h->f_trans_finish, Z, &a, s);
+  int rc = launch(h, h->f_trans_finish, std::min<int64_t>(Z, kFinishThreads), &a, s);
   h->profile = prof;
   if (rc) return rc;
   if (prof) {
@@ -762,7 +765,7 @@ int sweep(sdc_handle h, double dt, int k, const sdc_nodes& n, hipStream_t s) {
                                   : (kind == 1 ? (h->occ2 ? h->f_node0_o2 : h->f_node0)
                                                : (h->occ2 ? h->f_later_o2 : h->f_later));
       if ((rc = launch(h, f, h->P.Z, &a, s))) return rc;
-      if ((rc = launch(h, h->f_trans_finish, h->P.Z, &a, s))) return rc;
+      if ((rc = launch(h, h->f_trans_finish, std::min<int64_t>(h->P.Z, kFinishThreads), &a, s))) return rc;
     }
     if (h->P.cfg.advection) {
       rc = advect(h, n.U[m + 1], n.A[m + 1], s);
@@ -1335,7 +1338,7 @@ int sdc_reaction_solve(sdc_handle h, double dt_m, const double* rho, const doubl
   hipStream_t s = (hipStream_t)stream;
   if (int rc = reset_queue(h, s)) return rc;
   if (int rc = launch(h, h->occ2 ? h->f_solve_o2 : h->f_solve, h->P.Z, &a, s)) return rc;
-  return launch(h, h->f_solve_finish, h->P.Z, &a, s);
+  return launch(h, h->f_solve_finish, std::min<int64_t>(h->P.Z, kFinishThreads), &a, s);
 }
 
 int sdc_sweep(sdc_handle h, double dt, int32_t k, const sdc_nodes* nodes, void* stream) {
