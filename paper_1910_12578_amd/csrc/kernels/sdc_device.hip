@@ -353,6 +353,7 @@ __device__ __forceinline__ void advect_rows_body(const AdvArgs& a) {
       return v;
     };
     // ---- hydro: y and z faces from memory, stage the plane for x
+    __builtin_amdgcn_s_setprio(2);
     double Ay[SDC_NH], Az[SDC_NH];
     FaceHydro fy0, fy1, fz, fx;
     {
@@ -388,6 +389,7 @@ __device__ __forceinline__ void advect_rows_body(const AdvArgs& a) {
       }
     }
     Stencil7 nxt = load7(SDC_NH);  // first species, in flight across the hydro barriers
+    __builtin_amdgcn_s_setprio(0);
     __syncthreads();
     double Fx[SDC_NH];
     {
