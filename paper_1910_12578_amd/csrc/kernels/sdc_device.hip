@@ -270,16 +270,17 @@ __device__ __forceinline__ double slope_t(double um, double u0, double up) {
   return SLOPE == 0 ? 0.5 * (up - um) : mc_slope_of(um, u0, up);
 }
 
-template <int SLOPE>
+// BW: threads per block (256, or 512 for rows of 257..512 zones).
+template <int SLOPE, int BW>
 __device__ __forceinline__ void advect_rows_body(const AdvArgs& a) {
-  __shared__ double sh_u[SDC_NH][256];   // hydro components of the current plane
-  __shared__ double sh_fh[SDC_NH][256];  // hydro x-face fluxes
-  __shared__ double sh_s[2][256];        // one species component (alternating)
-  __shared__ double sh_fs[2][256];       // its x-face flux (alternating)
+  __shared__ double sh_u[SDC_NH][BW];   // hydro components of the current plane
+  __shared__ double sh_fh[SDC_NH][BW];  // hydro x-face fluxes
+  __shared__ double sh_s[2][BW];        // one species component (alternating)
+  __shared__ double sh_fs[2][BW];       // its x-face flux (alternating)
   const unsigned b = xcd_block(blockIdx.x, gridDim.x);
   const RowDesc d = a.rows[b];
   const int n0 = d.n0, n1 = d.n1, n2 = d.n2, ZC = d.zc;
-  const int R = 256 / n0;
+  const int R = BW / n0;
   const int t = threadIdx.x;
   const int r = t / n0, x = t - r * n0;
   const int slot = d.slot0 + r;
@@ -453,10 +454,17 @@ __device__ __forceinline__ void advect_rows_body(const AdvArgs& a) {
   }
 }
 extern "C" __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void sdc_advect_rows(AdvArgs a) {
-  advect_rows_body<1>(a);
+  advect_rows_body<1, 256>(a);
 }
 extern "C" __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void sdc_advect_rows_c(AdvArgs a) {
-  advect_rows_body<0>(a);
+  advect_rows_body<0, 256>(a);
+}
+// rows of 257..512 zones: one 512-thread block per CU, two waves per SIMD
+extern "C" __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void sdc_advect_rows_w(AdvArgs a) {
+  advect_rows_body<1, 512>(a);
+}
+extern "C" __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void sdc_advect_rows_wc(AdvArgs a) {
+  advect_rows_body<0, 512>(a);
 }
 #endif
 

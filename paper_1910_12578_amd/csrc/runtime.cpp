@@ -408,6 +408,7 @@ struct sdc_handle_s {
   int32_t* d_blk_box = nullptr;
   RowDesc* d_rows = nullptr;  // row advection kernel: one descriptor per block
   int64_t n_rows = 0;
+  int row_bw = 256;  // threads per block of the row kernel (512 for rows of 257..512 zones)
   int zchunk = 0;  // row kernel tile: planes per z chunk (0: heuristic)
   hipStream_t last_stream = nullptr;
   std::string err;
@@ -470,14 +471,14 @@ hipEvent_t take_event(sdc_handle h) {
   return e;
 }
 
-int launch_blocks(sdc_handle h, hipFunction_t f, int64_t nb, void* args, hipStream_t s);
+int launch_blocks(sdc_handle h, hipFunction_t f, int64_t nb, void* args, hipStream_t s, int block = kBlock);
 
 int launch(sdc_handle h, hipFunction_t f, int64_t nthreads, void* args, hipStream_t s) {
   if (nthreads <= 0) return SDC_OK;
   return launch_blocks(h, f, (nthreads + kBlock - 1) / kBlock, args, s);
 }
 
-int launch_blocks(sdc_handle h, hipFunction_t f, int64_t nb, void* args, hipStream_t s) {
+int launch_blocks(sdc_handle h, hipFunction_t f, int64_t nb, void* args, hipStream_t s, int block) {
   if (nb <= 0) return SDC_OK;
   void* params[] = {args};
   hipEvent_t ea = nullptr, eb = nullptr;
@@ -487,7 +488,7 @@ int launch_blocks(sdc_handle h, hipFunction_t f, int64_t nb, void* args, hipStre
     if (!ea || !eb) return fail(h, SDC_ERR_HIP, "hipEventCreate failed");
     HIP_CHECK(h, hipEventRecord(ea, s));
   }
-  HIP_CHECK(h, hipModuleLaunchKernel(f, (unsigned)nb, 1, 1, kBlock, 1, 1, 0, s, params, nullptr));
+  HIP_CHECK(h, hipModuleLaunchKernel(f, (unsigned)nb, 1, 1, (unsigned)block, 1, 1, 0, s, params, nullptr));
   if (h->profile) {
     HIP_CHECK(h, hipEventRecord(eb, s));
     h->timed.push_back({kind_of(h, f), ea, eb});
@@ -567,15 +568,15 @@ int reset_queue(sdc_handle h, hipStream_t s) {
 }
 
 // Blocks of the row advection kernel: every periodic grid (the domain, or
-// each box) is cut into slots (x-row y, z chunk), R = 256 / n0 slots per
+// each box) is cut into slots (x-row y, z chunk), R = bw / n0 slots per
 // block.  zmax = 0: the chunk starts at 32 planes and is halved until the
 // domain gives at least 2048 blocks (down to 4 planes); zmax > 0 (a tuned
 // tile): chunks of min(zmax, n2) planes.  A box's chunk is then halved until
 // its slots fill a block (down to 2 planes).
-std::vector<RowDesc> row_descriptors(const Prepared& P, int zmax) {
+std::vector<RowDesc> row_descriptors(const Prepared& P, int zmax, int bw) {
   std::vector<RowDesc> out;
   auto add_grid = [&](int64_t base, int n0, int n1, int n2, bool domain) {
-    const int R = kBlock / n0;
+    const int R = bw / n0;
     const int z0 = zmax > 0 ? zmax : 32;
     int zc = n2 < z0 ? n2 : z0;
     auto slots = [&](int z) { return (int64_t)n1 * ((n2 + z - 1) / z); };
@@ -607,23 +608,31 @@ std::vector<RowDesc> row_descriptors(const Prepared& P, int zmax) {
   return out;
 }
 
-// The row kernel takes 3D grids whose x-rows fit one block and whose
-// component arrays stay below 4 GiB (32-bit buffer offsets).
+// Longest x-row of the grid or of any box.
+int64_t longest_row(const Prepared& P) {
+  const sdc_config& c = P.cfg;
+  int64_t n0 = 0;
+  if (c.nbox > 0) {
+    for (int b = 0; b < c.nbox; ++b) n0 = std::max<int64_t>(n0, P.box_ext[3 * b]);
+    return n0;
+  }
+  return c.n[0];
+}
+
+// The row kernel takes 3D grids whose x-rows fit one block (256 threads, or
+// 512 for longer rows) and whose component arrays stay below 4 GiB (32-bit
+// buffer offsets).
+constexpr int64_t kRowMax = 512;
 bool rows_kernel_fits(const Prepared& P) {
   const sdc_config& c = P.cfg;
   if (c.dim != 3 || 8 * P.Z >= (int64_t(1) << 32)) return false;
-  if (c.nbox > 0) {
-    for (int b = 0; b < c.nbox; ++b)
-      if (P.box_ext[3 * b] > kBlock) return false;
-    return true;
-  }
-  return c.n[0] <= kBlock;
+  return longest_row(P) <= kRowMax;
 }
 
 // (Re)build the row descriptors for the current tile.
 int upload_rows(sdc_handle h) {
   if (!h->f_advect_rows) return SDC_OK;
-  const std::vector<RowDesc> rows = row_descriptors(h->P, h->zchunk);
+  const std::vector<RowDesc> rows = row_descriptors(h->P, h->zchunk, h->row_bw);
   if (h->d_rows && (int64_t)rows.size() > h->n_rows) {
     (void)hipFree(h->d_rows);
     h->d_rows = nullptr;
@@ -652,7 +661,7 @@ int advect(sdc_handle h, const double* U, double* A, hipStream_t s) {
   a.slope = c.slope;
   if (h->f_advect_rows) {
     a.rows = h->d_rows;
-    return launch_blocks(h, h->f_advect_rows, h->n_rows, &a, s);
+    return launch_blocks(h, h->f_advect_rows, h->n_rows, &a, s, h->row_bw);
   }
   if (c.nbox > 0) {
     a.nbox = c.nbox;
@@ -1220,12 +1229,16 @@ int sdc_init(const sdc_config* cfg, const sdc_network* net, sdc_handle* out) {
     e = hipModuleGetFunction(fn.f, h->mod, fn.name);
     if (e != hipSuccess) return bail(SDC_ERR_HIP, std::string("missing kernel ") + fn.name);
   }
-  // 3D single grids with rows of at most 256 zones and state arrays below
-  // 4 GiB (32-bit buffer offsets) use the row kernel (SDC_ADVECT_ROWS=0: the
-  // zone-per-thread kernel everywhere)
+  // 3D grids with rows of at most 512 zones and state arrays below 4 GiB
+  // (32-bit buffer offsets) use the row kernel, in 512-thread blocks when a
+  // row is longer than 256 zones (SDC_ADVECT_ROWS=0: the zone-per-thread
+  // kernel everywhere)
   const char* ev = std::getenv("SDC_ADVECT_ROWS");
   if (h->P.cfg.advection && rows_kernel_fits(h->P) && !(ev && ev[0] == '0')) {
-    const char* name = h->P.cfg.slope == 0 ? "sdc_advect_rows_c" : "sdc_advect_rows";
+    h->row_bw = longest_row(h->P) > kBlock ? 512 : kBlock;
+    const bool wide = h->row_bw > kBlock;
+    const char* name = h->P.cfg.slope == 0 ? (wide ? "sdc_advect_rows_wc" : "sdc_advect_rows_c")
+                                           : (wide ? "sdc_advect_rows_w" : "sdc_advect_rows");
     e = hipModuleGetFunction(&h->f_advect_rows, h->mod, name);
     if (e != hipSuccess) return bail(SDC_ERR_HIP, std::string("missing kernel ") + name);
     if (upload_rows(h) != SDC_OK) return bail(SDC_ERR_NOMEM, "row descriptors: " + h->err);

@@ -51,13 +51,15 @@ def test_advective_term(name, slope, alpha):
     assert_close(A, ref, 1e-11, f"A {name} slope={slope} alpha={alpha}")
 
 
-@pytest.mark.parametrize("shape", [(256, 2, 3), (257, 3, 2), (5, 7, 33), (64, 5, 4)])
+@pytest.mark.parametrize("shape", [(256, 2, 3), (257, 3, 2), (384, 2, 3), (512, 3, 2), (513, 2, 2),
+                                   (5, 7, 33), (64, 5, 4)])
 @pytest.mark.parametrize("slope", [1, 0])
 def test_advective_term_3d_edge_shapes(shape, slope):
     """3D grids at the edges of the row kernel: a full 256-zone row per block
-    with periodic images in y and z (n = 2, 3), rows longer than a block (the
-    zone-per-thread kernel), many rows per block with a z extent above one
-    chunk, and several rows per block."""
+    with periodic images in y and z (n = 2, 3), rows of 257..512 zones (the
+    512-thread blocks, with idle lanes and full), a row longer than any block
+    (the zone-per-thread kernel), many rows per block with a z extent above
+    one chunk, and several rows per block."""
     w, prob, h = make("net3d", shape=shape, slope=slope)
     U = w["U0"]
     A = to_np(h.advective_term(to_gpu(U.reshape(U.shape[0], -1))))
