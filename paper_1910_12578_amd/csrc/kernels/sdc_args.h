@@ -109,6 +109,14 @@ typedef struct {
   double v;
 } FillArgs;
 
+// Zero several arrays in one launch (the adjoint's accumulators).
+#define SDC_ZERO_MAX 12
+typedef struct {
+  double* p[SDC_ZERO_MAX];
+  sdc_i64 n[SDC_ZERO_MAX];
+  int count;
+} ZeroListArgs;
+
 // Adjoint of A (smooth mode: central slopes, frozen Rusanov speed):
 // Ubar += (dA/dU)^T Abar, evaluated at U, gather form.
 typedef struct {

@@ -1136,6 +1136,15 @@ extern "C" __global__ __launch_bounds__(256) void sdc_fill(FillArgs a) {
   if (i < a.n) a.p[i] = a.v;
 }
 
+// zeroes a.count arrays, every thread striding over each in turn
+extern "C" __global__ __launch_bounds__(256) void sdc_zero_list(ZeroListArgs a) {
+  const i64 stride = (i64)gridDim.x * blockDim.x;
+  for (int j = 0; j < a.count; ++j) {
+    double* __restrict__ p = a.p[j];
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < a.n[j]; i += stride) p[i] = 0.0;
+  }
+}
+
 // ====================================================================== adjoint
 // Reverse mode of the SDC step for gradients of a scalar objective with respect
 // to the state and the rate parameters theta = (lnA_r, E_r).  Each implicit

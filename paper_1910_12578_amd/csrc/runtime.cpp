@@ -400,7 +400,7 @@ struct sdc_handle_s {
   std::vector<hipEvent_t> batch_ev;
   double* split_buf = nullptr;  // [NX + 2][Z]
   hipFunction_t f_advect = nullptr, f_advect_rows = nullptr, f_source = nullptr, f_solve = nullptr, f_first = nullptr,
-                f_node0 = nullptr, f_later = nullptr, f_fill = nullptr;
+                f_node0 = nullptr, f_later = nullptr, f_fill = nullptr, f_zero_list = nullptr;
   void* d_params = nullptr;
   unsigned long long* d_stats = nullptr;
   int64_t* d_box_off = nullptr;
@@ -456,7 +456,7 @@ int kind_of(const sdc_handle h, hipFunction_t f) {
   if (f == h->f_node0 || f == h->f_node0_o2) return SDC_K_TRANSITION_NODE0;
   if (f == h->f_later || f == h->f_later_o2) return SDC_K_TRANSITION_LATER;
   if (f == h->f_reset) return SDC_K_FILL;
-  if (f == h->f_fill) return SDC_K_FILL;
+  if (f == h->f_fill || f == h->f_zero_list) return SDC_K_FILL;
   return SDC_K_ADJOINT;
 }
 
@@ -922,17 +922,34 @@ int step_adjoint(sdc_handle h, double dt, const double* Un, const double* Ubar1,
     for (int m = 1; m <= M; ++m)
       HIP_CHECK(h, hipMemcpyAsync(W.Ust[k][m], W.F.U[m], zc * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
-  // reverse
-  for (int j = 0; j <= M; ++j) {
-    if ((rc = fill(h, W.Ub[j], zc, 0.0, s)) || (rc = fill(h, W.Ab[j], zc, 0.0, s)) ||
-        (rc = fill(h, W.Rb[j], zr, 0.0, s)))
-      return rc;
+  // reverse (M + 1 <= 4 nodes: at most 12 arrays per zeroing launch)
+  {
+    ZeroListArgs z;
+    std::memset(&z, 0, sizeof z);
+    for (int j = 0; j <= M; ++j) {
+      z.p[z.count] = W.Ub[j];
+      z.n[z.count++] = zc;
+      z.p[z.count] = W.Ab[j];
+      z.n[z.count++] = zc;
+      z.p[z.count] = W.Rb[j];
+      z.n[z.count++] = zr;
+    }
+    if ((rc = launch(h, h->f_zero_list, std::min<int64_t>(zc, int64_t(4096) * kBlock), &z, s))) return rc;
   }
   HIP_CHECK(h, hipMemcpyAsync(W.Ub[M], Ubar1, zc * sizeof(double), hipMemcpyDeviceToDevice, s));
   const bool adv = h->P.cfg.advection != 0;
   for (int k = K - 1; k >= 0; --k) {
-    for (int j = 1; j <= M; ++j)
-      if ((rc = fill(h, W.Abo[j], zc, 0.0, s)) || (rc = fill(h, W.Rbo[j], zr, 0.0, s))) return rc;
+    {
+      ZeroListArgs z;
+      std::memset(&z, 0, sizeof z);
+      for (int j = 1; j <= M; ++j) {
+        z.p[z.count] = W.Abo[j];
+        z.n[z.count++] = zc;
+        z.p[z.count] = W.Rbo[j];
+        z.n[z.count++] = zr;
+      }
+      if ((rc = launch(h, h->f_zero_list, std::min<int64_t>(zc, int64_t(4096) * kBlock), &z, s))) return rc;
+    }
     if (adv && (rc = advect_vjp(h, W.Ust[k][M], W.Ab[M], W.Ub[M], s))) return rc;
     for (int m = M - 1; m >= 0; --m) {
       TransAdjArgs a;
@@ -964,11 +981,15 @@ int step_adjoint(sdc_handle h, double dt, const double* Un, const double* Ubar1,
     }
     // iteration k's node adjoints: the "old" accumulators; its states feed
     // only Newton guesses, so their adjoints restart from zero
+    ZeroListArgs z;
+    std::memset(&z, 0, sizeof z);
     for (int j = 1; j <= M; ++j) {
       std::swap(W.Ab[j], W.Abo[j]);
       std::swap(W.Rb[j], W.Rbo[j]);
-      if ((rc = fill(h, W.Ub[j], zc, 0.0, s))) return rc;
+      z.p[z.count] = W.Ub[j];
+      z.n[z.count++] = zc;
     }
+    if ((rc = launch(h, h->f_zero_list, std::min<int64_t>(zc, int64_t(4096) * kBlock), &z, s))) return rc;
   }
   // node 0: U^n itself, A^0 = A(U^n), R^0 = R(U^n)
   HIP_CHECK(h, hipMemcpyAsync(Ubar0, W.Ub[0], zc * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1215,7 +1236,7 @@ int sdc_init(const sdc_config* cfg, const sdc_network* net, sdc_handle* out) {
   } fns[] = {{&h->f_advect, "sdc_advect"},         {&h->f_source, "sdc_source"},
              {&h->f_solve, "sdc_reaction_solve"},  {&h->f_first, "sdc_transition_first"},
              {&h->f_node0, "sdc_transition_node0"}, {&h->f_later, "sdc_transition_later"},
-             {&h->f_fill, "sdc_fill"}, {&h->f_advect_vjp, "sdc_advect_vjp"},
+             {&h->f_fill, "sdc_fill"}, {&h->f_zero_list, "sdc_zero_list"}, {&h->f_advect_vjp, "sdc_advect_vjp"},
              {&h->f_trans_adj_first, "sdc_transition_adjoint_first"}, {&h->f_trans_adj, "sdc_transition_adjoint"},
              {&h->f_source_vjp, "sdc_source_vjp"}, {&h->f_theta_reduce, "sdc_theta_reduce"},
              {&h->f_axpy, "sdc_axpy"}, {&h->f_first_o2, "sdc_transition_first_o2"},
