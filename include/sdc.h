@@ -48,8 +48,8 @@ extern "C" {
 #define SDC_ERR_ARG 1         /* invalid argument or configuration */
 #define SDC_ERR_HIP 2         /* a HIP runtime call failed */
 #define SDC_ERR_NOMEM 3       /* device allocation failed */
-#define SDC_ERR_NEWTON 4      /* reserved: some zones did not converge (see sdc_stats) */
-#define SDC_ERR_NONFINITE 5   /* reserved: non-finite results (see sdc_stats) */
+#define SDC_ERR_NEWTON 4      /* sdc_check: some solves did not converge (outputs written, flagged) */
+#define SDC_ERR_NONFINITE 5   /* sdc_check: some solves gave non-finite results */
 #define SDC_ERR_UNSUPPORTED 6 /* configuration outside the supported range */
 #define SDC_ERR_COMPILE 7     /* run-time compilation of the kernels failed */
 
@@ -202,6 +202,15 @@ int sdc_step(sdc_handle h, double dt, int32_t nsteps, double* U, const sdc_nodes
 /* Copy the accumulated counters (SDC_STAT_*) to host `out[SDC_NSTATS]`;
  * synchronises the handle's last stream. */
 int sdc_stats(sdc_handle h, int64_t* out);
+
+/* Device-side outcome of the work since the last sdc_stats_reset, as a
+ * status: synchronises like sdc_stats, then returns SDC_ERR_NONFINITE if any
+ * solve gave a non-finite result, else SDC_ERR_NEWTON if any solve stopped
+ * at newton_maxiter without converging (its zone kept the last iterate and
+ * its iteration count reads -1), else SDC_OK.  sdc_last_error gives the
+ * counts.  Launch-time entry points never return these two codes: they
+ * enqueue work whose outcome is known only after it ran. */
+int sdc_check(sdc_handle h);
 
 /* Zero the counters (enqueued on `stream`). */
 int sdc_stats_reset(sdc_handle h, void* stream);

@@ -22,7 +22,7 @@ ERRORS = {1: "SDC_ERR_ARG", 2: "SDC_ERR_HIP", 3: "SDC_ERR_NOMEM", 4: "SDC_ERR_NE
           5: "SDC_ERR_NONFINITE", 6: "SDC_ERR_UNSUPPORTED", 7: "SDC_ERR_COMPILE"}
 EXPORTS = ("sdc_config_default", "sdc_init", "sdc_destroy", "sdc_last_error", "sdc_sizes",
            "sdc_advective_term", "sdc_source", "sdc_reaction_solve", "sdc_sweep", "sdc_step",
-           "sdc_stats", "sdc_stats_reset", "sdc_set_params", "sdc_compile_only",
+           "sdc_stats", "sdc_check", "sdc_stats_reset", "sdc_set_params", "sdc_compile_only",
            "sdc_generated_source", "sdc_aot_name", "sdc_profile_enable", "sdc_profile_read", "sdc_cost_model",
            "sdc_step_adjoint", "sdc_set_schedule", "sdc_get_schedule", "sdc_autotune")
 KINDS = ("advect", "source", "solve", "transition_first", "transition_node0", "transition_later", "fill",
@@ -81,6 +81,7 @@ def lib():
         L.sdc_sweep.argtypes = [c_void_p, c_double, c_int32, POINTER(Nodes), c_void_p]
         L.sdc_step.argtypes = [c_void_p, c_double, c_int32, c_void_p, POINTER(Nodes), c_void_p]
         L.sdc_stats.argtypes = [c_void_p, POINTER(c_int64)]
+        L.sdc_check.argtypes = [c_void_p]
         L.sdc_stats_reset.argtypes = [c_void_p, c_void_p]
         L.sdc_set_params.argtypes = [c_void_p, POINTER(c_double), POINTER(c_double)]
         L.sdc_compile_only.argtypes = [POINTER(Config), POINTER(Network)]
@@ -339,6 +340,16 @@ class SDC:
         _check(lib().sdc_stats(self._h, out), self._h)
         v = list(out)
         return dict(hist=v[0:16], failed=v[16], iters=v[17], nonfinite=v[18], solves=v[19], fallbacks=v[20])
+
+    def check(self):
+        """Device-side outcome since the last stats reset: 0 (all solves converged
+        and finite), 4 (SDC_ERR_NEWTON) or 5 (SDC_ERR_NONFINITE), with the
+        library's description of the counts."""
+        rc = lib().sdc_check(self._h)
+        if rc not in (0, 4, 5):
+            _check(rc, self._h)
+        msg = lib().sdc_last_error(self._h)
+        return rc, (msg.decode() if msg and rc else "")
 
     def stats_reset(self, stream=None):
         _check(lib().sdc_stats_reset(self._h, self._stream(stream)), self._h)

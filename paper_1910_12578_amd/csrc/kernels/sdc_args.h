@@ -109,8 +109,9 @@ typedef struct {
   double v;
 } FillArgs;
 
-// Zero several arrays in one launch (the adjoint's accumulators).
-#define SDC_ZERO_MAX 12
+// Zero several arrays in one launch (the adjoint's accumulators): up to three
+// per node (U, A and R adjoints) at the largest node count.
+#define SDC_ZERO_MAX (3 * SDC_MAXNODE)
 typedef struct {
   double* p[SDC_ZERO_MAX];
   sdc_i64 n[SDC_ZERO_MAX];

@@ -896,6 +896,28 @@ int advect_vjp(sdc_handle h, const double* U, const double* Abar, double* Ubar, 
   return launch(h, h->f_advect_vjp, h->P.Z, &a, s);
 }
 
+// The arrays of one sdc_zero_list launch.  add() refuses entries beyond
+// SDC_ZERO_MAX instead of writing past the argument block; zero_arrays()
+// then reports the overflow and launches nothing.
+struct ZeroList {
+  ZeroListArgs a;
+  bool overflow = false;
+  ZeroList() { std::memset(&a, 0, sizeof a); }
+  void add(double* p, int64_t n) {
+    if (a.count >= SDC_ZERO_MAX) {
+      overflow = true;
+      return;
+    }
+    a.p[a.count] = p;
+    a.n[a.count++] = n;
+  }
+};
+
+int zero_arrays(sdc_handle h, ZeroList& z, int64_t longest, hipStream_t s) {
+  if (z.overflow) return fail(h, SDC_ERR_UNSUPPORTED, "more arrays than one zeroing launch takes");
+  return launch(h, h->f_zero_list, std::min<int64_t>(longest, int64_t(4096) * kBlock), &z.a, s);
+}
+
 int theta_reduce(sdc_handle h, const double* part, double* thetabar, hipStream_t s) {
   if (h->P.topo.nr == 0) return SDC_OK;
   ThetaReduceArgs a{part, (h->P.Z + kBlock - 1) / kBlock, 2 * h->P.topo.nr, thetabar};
@@ -922,33 +944,26 @@ int step_adjoint(sdc_handle h, double dt, const double* Un, const double* Ubar1,
     for (int m = 1; m <= M; ++m)
       HIP_CHECK(h, hipMemcpyAsync(W.Ust[k][m], W.F.U[m], zc * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
-  // reverse (M + 1 <= 4 nodes: at most 12 arrays per zeroing launch)
+  // reverse: 3 (M + 1) <= SDC_ZERO_MAX arrays in the first zeroing launch
   {
-    ZeroListArgs z;
-    std::memset(&z, 0, sizeof z);
+    ZeroList z;
     for (int j = 0; j <= M; ++j) {
-      z.p[z.count] = W.Ub[j];
-      z.n[z.count++] = zc;
-      z.p[z.count] = W.Ab[j];
-      z.n[z.count++] = zc;
-      z.p[z.count] = W.Rb[j];
-      z.n[z.count++] = zr;
+      z.add(W.Ub[j], zc);
+      z.add(W.Ab[j], zc);
+      z.add(W.Rb[j], zr);
     }
-    if ((rc = launch(h, h->f_zero_list, std::min<int64_t>(zc, int64_t(4096) * kBlock), &z, s))) return rc;
+    if ((rc = zero_arrays(h, z, zc, s))) return rc;
   }
   HIP_CHECK(h, hipMemcpyAsync(W.Ub[M], Ubar1, zc * sizeof(double), hipMemcpyDeviceToDevice, s));
   const bool adv = h->P.cfg.advection != 0;
   for (int k = K - 1; k >= 0; --k) {
     {
-      ZeroListArgs z;
-      std::memset(&z, 0, sizeof z);
+      ZeroList z;
       for (int j = 1; j <= M; ++j) {
-        z.p[z.count] = W.Abo[j];
-        z.n[z.count++] = zc;
-        z.p[z.count] = W.Rbo[j];
-        z.n[z.count++] = zr;
+        z.add(W.Abo[j], zc);
+        z.add(W.Rbo[j], zr);
       }
-      if ((rc = launch(h, h->f_zero_list, std::min<int64_t>(zc, int64_t(4096) * kBlock), &z, s))) return rc;
+      if ((rc = zero_arrays(h, z, zc, s))) return rc;
     }
     if (adv && (rc = advect_vjp(h, W.Ust[k][M], W.Ab[M], W.Ub[M], s))) return rc;
     for (int m = M - 1; m >= 0; --m) {
@@ -981,15 +996,13 @@ int step_adjoint(sdc_handle h, double dt, const double* Un, const double* Ubar1,
     }
     // iteration k's node adjoints: the "old" accumulators; its states feed
     // only Newton guesses, so their adjoints restart from zero
-    ZeroListArgs z;
-    std::memset(&z, 0, sizeof z);
+    ZeroList z;
     for (int j = 1; j <= M; ++j) {
       std::swap(W.Ab[j], W.Abo[j]);
       std::swap(W.Rb[j], W.Rbo[j]);
-      z.p[z.count] = W.Ub[j];
-      z.n[z.count++] = zc;
+      z.add(W.Ub[j], zc);
     }
-    if ((rc = launch(h, h->f_zero_list, std::min<int64_t>(zc, int64_t(4096) * kBlock), &z, s))) return rc;
+    if ((rc = zero_arrays(h, z, zc, s))) return rc;
   }
   // node 0: U^n itself, A^0 = A(U^n), R^0 = R(U^n)
   HIP_CHECK(h, hipMemcpyAsync(Ubar0, W.Ub[0], zc * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1508,6 +1521,16 @@ int sdc_stats(sdc_handle h, int64_t* out) {
   unsigned long long tmp[SDC_NSTATS];
   HIP_CHECK(h, hipMemcpy(tmp, h->d_stats, sizeof tmp, hipMemcpyDeviceToHost));
   for (int i = 0; i < SDC_NSTATS; ++i) out[i] = (int64_t)tmp[i];
+  return SDC_OK;
+}
+
+int sdc_check(sdc_handle h) {
+  int64_t st[SDC_NSTATS];
+  if (int rc = sdc_stats(h, st)) return rc;
+  const std::string counts = std::to_string(st[SDC_STAT_FAILED]) + " of " + std::to_string(st[SDC_STAT_SOLVES]) +
+                             " solves unconverged, " + std::to_string(st[SDC_STAT_NONFINITE]) + " non-finite";
+  if (st[SDC_STAT_NONFINITE] > 0) return fail(h, SDC_ERR_NONFINITE, counts);
+  if (st[SDC_STAT_FAILED] > 0) return fail(h, SDC_ERR_NEWTON, counts);
   return SDC_OK;
 }
 

@@ -117,7 +117,7 @@ def conserved_from_primitive(rho, u, p, X, gamma=GAMMA) -> np.ndarray:
     """Stack (rho, rho u_d, rho E, rho X_s) into U[comp, *grid] (x fastest)."""
     dim = len(u)
     nspec = X.shape[0]
-    U = np.empty((2 + dim + nspec,) + rho.shape)
+    U = np.empty((2 + dim + nspec,) + rho.shape, dtype=np.result_type(rho, p, X, *u))
     U[0] = rho
     ke = np.zeros_like(rho)
     for d in range(dim):

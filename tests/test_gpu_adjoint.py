@@ -53,6 +53,38 @@ def test_parameter_gradient_matches_finite_differences():
     assert np.all(err <= 1e-6), (g, fd)
 
 
+@pytest.mark.parametrize("n_nodes", [4, 5])
+def test_parameter_gradient_at_four_and_five_nodes(n_nodes):
+    """Regression: the adjoint at 4 and 5 Gauss-Lobatto nodes, where the first
+    zeroing launch of the reverse pass takes 3 (M + 1) = 12 and 15 arrays
+    (every node's U, A and R adjoints), against central differences of the
+    GPU forward on the parameters with the largest gradients."""
+    import torch
+    from paper_1910_12578_amd.autograd import theta_of
+    print(f"adjoint at {n_nodes} nodes", flush=True)
+    w, h, q = setup(shape=(12, 10), n_nodes=n_nodes, n_iters=3)
+    nsteps = 2
+    nc = w["U0"].shape[0]
+    U0 = to_gpu(w["U0"].reshape(nc, -1))
+    theta = theta_of(w["network"]).requires_grad_(True)
+    J = objective(h, w, q, U0, theta, nsteps)
+    J.backward()
+    g = theta.grad.numpy()
+    nr = w["network"]["nreact"]
+    picks = np.argsort(-np.abs(g))[:6]
+    fd = np.zeros(picks.size)
+    for i, p in enumerate(picks):
+        hstep = 1e-4 if p < nr else 1e-4 * w["network"]["E"][p - nr]
+        with torch.no_grad():
+            tp, tm = theta.detach().clone(), theta.detach().clone()
+            tp[p] += hstep
+            tm[p] -= hstep
+            fd[i] = (objective(h, w, q, U0, tp, nsteps).item() - objective(h, w, q, U0, tm, nsteps).item()) / (2 * hstep)
+    err = np.abs(g[picks] - fd) / np.abs(fd)
+    print(f"{n_nodes} nodes: adjoint vs FD max relative error {err.max():.2e}")
+    assert np.all(err <= 1e-6), (g[picks], fd)
+
+
 def test_parameter_gradient_matches_oracle_complex_step():
     import torch
     from paper_1910_12578_amd.autograd import theta_of

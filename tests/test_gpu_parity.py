@@ -185,6 +185,9 @@ def test_unconverged_zones_are_flagged():
     assert_close(to_np(xg), x, TOL_FP64, "kept last iterate")
     s = h.stats()
     assert s["failed"] == s["solves"] == x.shape[1]
+    assert h.check()[0] == 4  # SDC_ERR_NEWTON
+    h.stats_reset()
+    assert h.check() == (0, "")
 
 
 def test_non_finite_zone_is_counted_not_fatal():
@@ -197,6 +200,7 @@ def test_non_finite_zone_is_counted_not_fatal():
     assert nug[5] == -1 and np.all(np.delete(nug, 5) > 0)
     s = h.stats()
     assert s["nonfinite"] >= 1 and s["failed"] == 1
+    assert h.check()[0] == 5  # SDC_ERR_NONFINITE
     ok = np.ones(b.shape[1], bool)
     ok[5] = False
     x, _, _ = osdc.reaction_solve(w["dt"], rho[ok], b[:, ok], x0[:, ok], prob)
