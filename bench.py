@@ -8,16 +8,21 @@ MC slopes and local Rusanov speeds, CFL time step.  A step is one full pass of
 the hot path: 4 iterations x 2 node transitions (fused quadrature, explicit
 update and per-zone Newton) plus the advective term at every new node.  Inputs
 are resident in HBM before the timed region, which brackets exactly K steps
-with device synchronisation.  Prints one JSON line.
+with device synchronisation and no per-launch instrumentation.  Prints one
+JSON line.
 
 The FP64 path gives `value`; the mixed path (FP32 Newton matrix and LU) is
-reported beside it.  `roofline` covers the dominant kernel (the fused m = 0
-node transition, sdc_transition_node0), timed with HIP events on the launch
-stream inside the timed region, against the ceiling its algorithmic bytes and
-flops make binding; `traffic` is the HBM bytes per launch from the committed
-counter summary when that was taken on the same kernel source.
-`cpu_baseline` times the CPU oracle on a bounded sub-volume of the same
-workload (single thread).
+reported beside it, and so are the 2D 512^2 workload (7 species), the
+batched-box workload (plain launches and captured graphs, with its Newton
+iteration histogram) and the adjoint/forward time ratio.  After the timed
+steps, the same number of steps runs again with HIP events around every
+launch (on the launch stream): `kernels` lists each kernel's summed and mean
+launch time, share and fraction of the HBM and FP64 ceilings, and `roofline`
+covers the kernel with the largest summed time, against the ceiling its
+algorithmic bytes and flops make binding; `traffic` is the HBM bytes per
+launch from the committed counter summary when that was taken on the same
+kernel source.  `cpu_baseline` times the CPU oracle on sub-blocks of the same
+workload, one process per core the job may use.
 """
 from __future__ import annotations
 
@@ -38,7 +43,7 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X vector FP64 (FMA counts 2)
 PEAK_HBM_GBS = 8000.0
 
 
-def kernel_model(h, stats):
+def kernel_model(h, stats, dim):
     """Algorithmic FP64 bytes and flops per zone of each kernel launch.
 
     Bytes: every state, advective, source and correction array a kernel reads
@@ -47,8 +52,10 @@ def kernel_model(h, stats):
     generated network code (exp and log count one each) plus 2 n_x for the
     update and the test; a solve adds one R(x) at the root and the explicit
     update (about 4 n_c); the quadrature of the m = 0 transition adds
-    2 (M+1)(n_c + n_x) per correction term.  The Newton count is the measured
-    mean over the timed steps.
+    2 (M+1)(n_c + n_x) per correction term.  The advective term counts, per
+    direction, the reconstruction and Rusanov flux of every component
+    ((9 n_c + 40 + 3 n_c) per face) and the divergence (2 n_c).  The Newton
+    count is the measured mean over the timed steps.
     """
     cm = h.cost_model()
     nx, nc, M = h.nreact_vars, h.ncomp, h.n_nodes - 1
@@ -67,6 +74,8 @@ def kernel_model(h, stats):
         "transition_first": newton + 2 * nc,
         "transition_node0": newton + 2 * (M + 1) * (nc + nx) * M,
         "transition_later": newton + 3 * nc,
+        "advect": ((9 * nc + 40 + 3 * nc) + 2 * nc) * dim,
+        "source": cm["source"],
     }
     return {k: 8.0 * v for k, v in words.items()}, flops, per_iter, per_solve
 
@@ -85,25 +94,35 @@ def roofline(bytes_per_zone, flops_per_zone, zones, avg_s):
                 hbm_frac=hbm["frac"], alu_frac=alu["frac"], alu_TFLOPs=alu["achieved"], hbm_GBs=hbm["achieved"])
 
 
+def kernel_name(kind, dim, sched, precision):
+    """Name of the kernel that a profiled kind stands for under a schedule."""
+    if kind == "advect":
+        return "sdc_advect_rows" if dim == 3 else "sdc_advect"
+    if kind.startswith("transition_"):
+        return "sdc_" + kind + ("_o2" if sched["occ2"] else "")
+    return "sdc_" + kind
+
+
 def recorded_traffic(h, kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    if it was taken on this kernel and on the source this handle compiled
-    (else None)."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_sdc_transition_node0_net3d_256cubed.md")
-    if not os.path.exists(path):
-        return None, None
-    rec = {}
-    with open(path) as f:
-        for line in f:
-            if line.startswith("- ") and ": " in line:
-                k, v = line[2:].split(": ", 1)
-                rec[k.strip()] = v.strip().strip("`")
+    """HBM bytes per launch of `kernel` from the committed counter summaries
+    (profiles/hbm_traffic_*.md), if one was taken on this kernel and on the
+    source this handle compiled (else None).  A summary's machine-readable
+    record holds `source_sha256_16` and one `traffic_bytes_per_launch[<kernel>]`
+    line per kernel."""
+    import glob
     import hashlib
-    src = h.generated_source()
-    digest = hashlib.sha256(src.encode()).hexdigest()[:16]
-    if rec.get("source_sha256_16") != digest or rec.get("kernel") != kernel or "traffic_bytes_per_launch" not in rec:
-        return None, digest
-    return float(rec["traffic_bytes_per_launch"]), digest
+    digest = hashlib.sha256(h.generated_source().encode()).hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md"))):
+        rec = {}
+        with open(path) as f:
+            for line in f:
+                if line.startswith("- ") and ": " in line:
+                    k, v = line[2:].split(": ", 1)
+                    rec[k.strip()] = v.strip().strip("`")
+        key = f"traffic_bytes_per_launch[{kernel}]"
+        if rec.get("source_sha256_16") == digest and key in rec:
+            return float(rec[key]), digest
+    return None, digest
 
 
 def make_handle(w, precision, schedule, graph=0):
@@ -134,9 +153,39 @@ def warm(h, dt, U, work, warmup, schedule):
                 warmup_s=round(time.perf_counter() - t0, 3))
 
 
-def run_gpu(w, precision, steps, warmup, schedule="auto"):
+def kernel_table(h, w, st, prof, sched, precision):
+    """Per-kernel summary of a profiled pass: summed and mean launch time,
+    share of the kernel time, algorithmic bytes per launch and the fraction of
+    the HBM and FP64 ceilings each reaches; the dominant kernel (largest summed
+    time) and its roofline."""
+    Z = w["U0"][0].size
+    bpz, fpz, per_iter, per_solve = kernel_model(h, st, w["dim"])
+    total = sum(v[0] for v in prof.values())
+    table = {}
+    for k, (ms, n) in prof.items():
+        if not n:
+            continue
+        row = dict(ms=round(ms, 3), launches=n, avg_ms=round(ms / n, 4), share=round(ms / total, 4))
+        if k in bpz:
+            r = roofline(bpz[k], fpz.get(k, 0.0), Z, ms * 1e-3 / n)
+            row.update(bytes_per_zone=bpz[k], hbm_frac=round(r["hbm_frac"], 4), fp64_frac=round(r["alu_frac"], 4))
+        table[k] = row
+    dom = max(table, key=lambda k: table[k]["ms"])
+    roof = roofline(bpz[dom], fpz.get(dom, 0.0), Z, prof[dom][0] * 1e-3 / prof[dom][1])
+    kname = kernel_name(dom, w["dim"], sched, precision)
+    roof["traffic"], digest = recorded_traffic(h, kname)
+    roof["kernel"] = kname
+    roof["share"] = table[dom]["share"]
+    step_bytes = sum(bpz[k] * Z * prof[k][1] for k in bpz if prof[k][1])
+    return table, roof, step_bytes, digest, per_iter, per_solve
+
+
+def run_gpu(w, precision, steps, warmup, schedule="auto", graph=0):
+    """Timed steps with profiling off (value, ms_per_step), then the same
+    number of steps with HIP events around every launch (per-kernel table and
+    roofline of the dominant kernel)."""
     import torch
-    h = make_handle(w, precision, schedule)
+    h = make_handle(w, precision, schedule, graph=graph)
     nc = w["U0"].shape[0]
     U = torch.from_numpy(w["U0"].reshape(nc, -1)).to("cuda")
     work = h.alloc_nodes()
@@ -144,35 +193,30 @@ def run_gpu(w, precision, steps, warmup, schedule="auto"):
     stream = torch.cuda.current_stream()
     sched = warm(h, dt, U, work, warmup, schedule)
     h.stats_reset()
-    h.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     h.step(dt, steps, U, work, stream=stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    prof = h.profile_read()
-    h.profile(False)
     st = h.stats()
+    check = h.check()[0]
     ok = bool(torch.isfinite(U).all().item())
     Z = w["U0"][0].size
-    bpz, fpz, per_iter, per_solve = kernel_model(h, st)
-    # the dominant kernel: the m = 0 transition (quadrature of every node,
-    # correction terms, explicit update, Newton), timed with HIP events
-    dom = "transition_node0"
-    avg = prof[dom][0] * 1e-3 / max(prof[dom][1], 1)
-    roof = roofline(bpz[dom], fpz[dom], Z, avg)
-    kname = "sdc_" + dom + ("_o2" if sched["occ2"] else "")
-    traffic, digest = recorded_traffic(h, kname)
-    roof["traffic"] = traffic
-    roof["kernel"] = kname
-    # whole step against the HBM roofline: every launch's algorithmic bytes
-    step_bytes = sum(bpz[k] * Z * prof[k][1] for k in bpz if prof[k][1])
+    h.profile(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    h.step(dt, steps, U, work, stream=stream)
+    torch.cuda.synchronize()
+    elapsed_prof = time.perf_counter() - t1
+    prof = h.profile_read()
+    h.profile(False)
+    table, roof, step_bytes, digest, per_iter, per_solve = kernel_table(h, w, st, prof, sched, precision)
     res = dict(
         elapsed=elapsed, ms_per_step=1e3 * elapsed / steps, zone_updates=Z * steps / elapsed,
         zone_sweeps=Z * steps * w["n_iters"] / elapsed,
-        stats=st, mean_newton=st["iters"] / max(st["solves"] - st["failed"], 1), finite=ok,
-        profile={k: dict(ms=round(v[0], 3), launches=v[1]) for k, v in prof.items() if v[1]},
-        roofline=roof, step_hbm_frac=step_bytes / elapsed / (PEAK_HBM_GBS * 1e9),
+        ms_per_step_profiled=1e3 * elapsed_prof / steps,
+        stats=st, mean_newton=st["iters"] / max(st["solves"] - st["failed"], 1), finite=ok, check=check,
+        kernels=table, roofline=roof, step_hbm_frac=step_bytes / elapsed_prof / (PEAK_HBM_GBS * 1e9),
         flops_per_newton_iteration=per_iter, flops_per_solve=per_solve,
         cost_model=h.cost_model(), schedule=sched, source_sha256_16=digest,
     )
@@ -228,20 +272,20 @@ def run_adjoint_ratio(nsteps=20):
                 forward_ms=1e3 * (t1 - t0), backward_ms=1e3 * (t2 - t1), ratio=(t2 - t1) / (t1 - t0))
 
 
-def run_boxes(steps, warmup, precision, schedule="auto"):
-    """Batched boxes: 4096 periodic boxes, edges in {8,16,32,64}, one launch
-    per kernel over all boxes; then the same steps replayed from captured HIP
+def run_boxes(w, steps, warmup, precision, schedule="auto"):
+    """Batched boxes: independent periodic boxes of uneven size, one launch per
+    kernel over all boxes; then the same steps replayed from captured HIP
     graphs (one per buffer-rotation phase of a step)."""
     import torch
-    w = si.boxes_workload()
     Z = w["U0"].shape[1]
-    out = dict(workload=f"{len(w['box_n'])} boxes, edges in {{8,16,32,64}}, {Z} zones, 0.2 CFL step")
+    out = {}
     for graph in (0, 1):
         h = make_handle(w, precision, schedule, graph=graph)
         U = torch.from_numpy(w["U0"]).to("cuda")
         work = h.alloc_nodes()
         sched = warm(h, w["dt"], U, work, max(warmup, 1) if graph else warmup, schedule)
         h.stats_reset()
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         h.step(w["dt"], steps, U, work)
         torch.cuda.synchronize()
@@ -252,7 +296,8 @@ def run_boxes(steps, warmup, precision, schedule="auto"):
         else:
             out.update(zone_updates=Z * steps / el, ms_per_step=1e3 * el / steps,
                        mean_newton=st["iters"] / max(st["solves"] - st["failed"], 1), failed=st["failed"],
-                       newton_hist={i: v for i, v in enumerate(st["hist"]) if v}, schedule=sched)
+                       nonfinite=st["nonfinite"], newton_hist={i: v for i, v in enumerate(st["hist"]) if v},
+                       schedule=sched)
         h.close()
         del U, work
         torch.cuda.empty_cache()
@@ -274,6 +319,14 @@ def _oracle_block(args):
 def _warm_worker(_):
     from oracle import sdc as osdc  # noqa: F401  (import cost outside the timed map)
     return 0
+
+
+def host_cores():
+    """Cores this job may use: the CPU affinity set, bounded by OMP_NUM_THREADS
+    when the environment sets it (the CPU share given to a one-GPU job)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, min(n, int(omp))) if omp.isdigit() and int(omp) > 0 else n
 
 
 def cpu_baseline(w, edge, procs):
@@ -310,6 +363,34 @@ def cpu_baseline(w, edge, procs):
     return out
 
 
+def workload_label(w):
+    grid = "x".join(map(str, w["shape"])) if w.get("shape") else f"{len(w['box_n'])} boxes"
+    nodes = "Radau" if w.get("node_type") == "radau" else "Gauss-Lobatto"
+    return (f"{w['name']} {grid}, {w['network']['nspec']} species / {w['network']['nreact']} reactions, "
+            f"{w['n_nodes']} {nodes} nodes, K={w['n_iters']}")
+
+
+def gpu_leg(w, steps, warmup, schedule, precisions=("fp64", "mixed")):
+    """FP64 and mixed runs of one single-grid workload, summarised."""
+    out = {}
+    for name in precisions:
+        prec = 0 if name == "fp64" else 1
+        print(f"[bench] {w['name']} {name}: warmup {warmup}, timed {steps} steps", file=sys.stderr, flush=True)
+        out[name] = run_gpu(w, prec, steps, warmup, schedule)
+        print(f"[bench] {w['name']} {name}: {out[name]['zone_updates']:.4e} zone-updates/s "
+              f"({out[name]['ms_per_step']:.2f} ms/step)", file=sys.stderr, flush=True)
+    return out
+
+
+def summary(r):
+    return dict(value=r["zone_updates"], ms_per_step=r["ms_per_step"],
+                ms_per_step_profiled=r["ms_per_step_profiled"], mean_newton_iterations=r["mean_newton"],
+                newton_failed=r["stats"]["failed"], schedule=r["schedule"],
+                roofline={k: r["roofline"][k] for k in ("kernel", "share", "bound", "frac", "achieved", "unit",
+                                                        "avg_launch_ms", "hbm_frac", "alu_frac", "traffic")},
+                step_hbm_frac=r["step_hbm_frac"], kernels=r["kernels"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -319,11 +400,12 @@ def main():
     ap.add_argument("--shape", default=None, help="override grid, e.g. 64,64,64")
     ap.add_argument("--precision", default="both", choices=("fp64", "mixed", "both"))
     ap.add_argument("--cpu-edge", type=int, default=48)
-    ap.add_argument("--cpu-procs", type=int, default=min(16, os.cpu_count() or 1),
-                    help="oracle worker processes for cpu_baseline (one thread each)")
+    ap.add_argument("--cpu-procs", type=int, default=0,
+                    help="oracle worker processes for cpu_baseline, one thread each (0: every core the job may use)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward time ratio")
-    ap.add_argument("--boxes", action="store_true", help="also time the 4096-box batched workload")
+    ap.add_argument("--no-boxes", action="store_true", help="skip the batched-box workload")
+    ap.add_argument("--no-net2d", action="store_true", help="skip the 2D 512^2 workload")
     ap.add_argument("--schedule", default="auto",
                     help="schedule: 'auto' (tuned on the first warmup step) or 'OCC2,CAP[,SPLIT[,ZCHUNK]]', e.g. 0,0,0,16")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -337,16 +419,13 @@ def main():
     print(f"[bench] generating {a.workload} {shape or ''}", file=sys.stderr, flush=True)
     w = si.workload(a.workload, shape=shape)
     Z = w["U0"][0].size
-    runs = {}
-    for name, prec in (("fp64", 0), ("mixed", 1)):
-        if a.precision in (name, "both"):
-            print(f"[bench] {name}: warmup {a.warmup}, timed {a.steps} steps", file=sys.stderr, flush=True)
-            runs[name] = run_gpu(w, prec, a.steps, a.warmup, a.schedule)
-            print(f"[bench] {name}: {runs[name]['zone_updates']:.4e} zone-updates/s", file=sys.stderr, flush=True)
+    precs = ("fp64", "mixed") if a.precision == "both" else (a.precision,)
+    runs = gpu_leg(w, a.steps, a.warmup, a.schedule, precs)
     head = runs.get("fp64") or runs["mixed"]
-    roof = dict(head["roofline"])
+    label = workload_label(w)
     out = dict(
-        metric="SDC zone-updates/s, 256^3 x 13 species, FP64 (mixed and adjoint/forward time beside it)",
+        metric=f"SDC zone-updates/s, {label}, {'FP64' if 'fp64' in runs else 'mixed'} "
+               f"(mixed precision, other workloads and adjoint/forward time beside it)",
         value=head["zone_updates"],
         unit="zone-updates/s",
         n_gpus=1, steps=a.steps, warmup=a.warmup,
@@ -354,33 +433,43 @@ def main():
         higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype="f64" if "fp64" in runs else "f64+f32lu",
         data="synthetic",
-        config=dict(workload=f"{a.workload} {'x'.join(map(str, w['shape']))}, {w['network']['nspec']} species / "
-                             f"{w['network']['nreact']} reactions, {w['n_nodes']} Gauss-Lobatto nodes, "
-                             f"K={w['n_iters']}", zones=Z, dt=w["dt"]),
-        roofline=roof,
+        config=dict(workload=label, zones=Z, dt=w["dt"]),
+        roofline=dict(head["roofline"]),
         step_hbm_frac=head["step_hbm_frac"],
         zone_sweeps_per_s=head["zone_sweeps"],
+        ms_per_step_profiled=head["ms_per_step_profiled"],
         schedule=head["schedule"],
         mean_newton_iterations=head["mean_newton"],
         newton_failed=head["stats"]["failed"],
         newton_hist={i: v for i, v in enumerate(head["stats"]["hist"]) if v},
-        kernels_ms=head["profile"],
+        kernels=head["kernels"],
     )
     if "mixed" in runs and "fp64" in runs:
-        mx = runs["mixed"]
-        out["mixed"] = dict(value=mx["zone_updates"], ms_per_step=mx["ms_per_step"],
-                            speedup_vs_fp64=mx["zone_updates"] / runs["fp64"]["zone_updates"],
-                            mean_newton_iterations=mx["mean_newton"], schedule=mx["schedule"],
-                            roofline={k: mx["roofline"][k] for k in ("kernel", "bound", "frac", "achieved", "unit",
-                                                                     "avg_launch_ms", "hbm_frac", "alu_frac")},
-                            step_hbm_frac=mx["step_hbm_frac"], kernels_ms=mx["profile"])
+        out["mixed"] = summary(runs["mixed"])
+        out["mixed"]["speedup_vs_fp64"] = runs["mixed"]["zone_updates"] / runs["fp64"]["zone_updates"]
+    others = {}
+    if not a.no_net2d and a.workload != "net2d" and shape is None:
+        w2 = si.workload("net2d")
+        r2 = gpu_leg(w2, a.steps, a.warmup, a.schedule, precs)
+        others["net2d"] = dict(workload=workload_label(w2), zones=w2["U0"][0].size,
+                               **{k: summary(v) for k, v in r2.items()})
+        del w2
+    if not a.no_boxes and shape is None:
+        print("[bench] generating batched boxes", file=sys.stderr, flush=True)
+        wb = si.boxes_workload()
+        Zb = wb["U0"].shape[1]
+        box = dict(workload=workload_label(wb) + f", {Zb} zones, dt {wb['dt']:.3e}", zones=Zb)
+        for name in precs:
+            print(f"[bench] boxes {name}", file=sys.stderr, flush=True)
+            box[name] = run_boxes(wb, a.steps, a.warmup, 0 if name == "fp64" else 1, a.schedule)
+            print(f"[bench] boxes {name}: {box[name]['zone_updates']:.4e} zone-updates/s", file=sys.stderr, flush=True)
+        others["boxes"] = box
+        del wb
+    if others:
+        out["workloads"] = others
     if not a.no_adjoint:
         print("[bench] adjoint/forward ratio", file=sys.stderr, flush=True)
         out["adjoint"] = run_adjoint_ratio()
-    if a.boxes:
-        print("[bench] batched boxes", file=sys.stderr, flush=True)
-        out["boxes"] = {name: run_boxes(a.steps, a.warmup, prec, a.schedule)
-                        for name, prec in (("fp64", 0), ("mixed", 1))}
     if a.copy_probe_mib:
         import torch
         n = a.copy_probe_mib * (1 << 20) // 8
@@ -392,8 +481,9 @@ def main():
         out["copy_probe_bytes"] = 8 * n
         del src, dst
     if not a.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, a.cpu_edge, a.cpu_procs)
+        procs = a.cpu_procs or host_cores()
+        print(f"[bench] cpu baseline (oracle, {procs} processes)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_edge, procs)
     print(json.dumps(out), flush=True)
 
 
