@@ -47,6 +47,7 @@ class Problem:
     gamma: float
     net: dict
     n_nodes: int = 3
+    node_type: str = "lobatto"  # or 'radau' (right Radau points, see quadrature.py)
     n_iters: int = 4
     slope: int = 1
     alpha: float = -1.0
@@ -70,7 +71,7 @@ class Problem:
         kw = dict(dim=w["dim"], shape=w["shape"], dx=w["dx"], gamma=w["gamma"],
                   net=w["network"], n_nodes=w["n_nodes"], n_iters=w["n_iters"],
                   slope=w["slope"], alpha=w["alpha"], newton_tol=w["newton_tol"],
-                  newton_maxiter=w["newton_maxiter"])
+                  newton_maxiter=w["newton_maxiter"], node_type=w.get("node_type", "lobatto"))
         kw.update(over)
         return cls(**kw)
 
@@ -186,8 +187,7 @@ def reaction_solve(dtm, rho, b, x0, prob: Problem):
 
 # ------------------------------------------------------------------- sweep
 def node_times(prob: Problem):
-    tau = quadrature.gauss_lobatto_nodes(prob.n_nodes)
-    return tau, quadrature.integration_matrix(tau)
+    return quadrature.node_set(prob.node_type, prob.n_nodes)
 
 
 def sweep(Un, A, R, U, dt, prob: Problem, stats: Stats | None = None):
