@@ -29,6 +29,17 @@ Readings where the paper is silent:
 * R^{m+1,(k+1)} is R re-evaluated at the converged x;
 * A^0 and R^0 of step n+1 are A^{M,(K)} and R^{M,(K)} of step n (the same
   state; `run` carries them over).
+
+Fourth order in space (space_order = 4, the paper's fourth-order method with
+Simpson's rule in time; pieces in `fourth_order.py`): A is the fourth-order
+zone-average advective term, and the reactive terms are zone averages of the
+source at zone-centre states.  Reading of the implicit part: the right-hand
+side of Eq. 2 (zone averages) is converted to zone-centre values, the Newton
+solve runs on those (same guess, stopping rule and unknowns as above), the
+source at the centre root is converted back to a zone average <R>, and the
+new state is rhs + dt_m <R> (rho and rho u are the rhs: <R> is zero there).
+R(U^n) at the start of a step is likewise the average of R at the centre
+values of U^n.
 """
 from __future__ import annotations
 
@@ -36,7 +47,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import advection, network, quadrature
+from . import advection, fourth_order, network, quadrature
 
 
 @dataclass
@@ -55,6 +66,7 @@ class Problem:
     newton_tol: float = 1e-13
     newton_maxiter: int = 50
     newton_extra: int = 0   # extra iterations after convergence (complex step)
+    space_order: int = 2    # 4: fourth-order advective term and zone-average sources
     lnA: np.ndarray = None  # rate parameters (override the network's)
     E: np.ndarray = None
 
@@ -71,7 +83,8 @@ class Problem:
         kw = dict(dim=w["dim"], shape=w["shape"], dx=w["dx"], gamma=w["gamma"],
                   net=w["network"], n_nodes=w["n_nodes"], n_iters=w["n_iters"],
                   slope=w["slope"], alpha=w["alpha"], newton_tol=w["newton_tol"],
-                  newton_maxiter=w["newton_maxiter"], node_type=w.get("node_type", "lobatto"))
+                  newton_maxiter=w["newton_maxiter"], node_type=w.get("node_type", "lobatto"),
+                  space_order=w.get("space_order", 2))
         kw.update(over)
         return cls(**kw)
 
@@ -95,6 +108,8 @@ class Stats:
 def A_of(U, prob: Problem):
     if not prob.advection:
         return np.zeros_like(U)
+    if prob.space_order == 4:
+        return fourth_order.advective_term4(U, prob.dim, prob.dx, prob.gamma)
     return advection.advective_term(U, prob.dim, prob.dx, prob.gamma, prob.slope, prob.alpha)
 
 
@@ -130,6 +145,15 @@ def R_full_from_x(x, prob: Problem):
 
 
 def R_of_state(U, prob: Problem):
+    """R(U) on a full-length layout; at fourth order the zone average of R
+    at the zone-centre values of U."""
+    if prob.space_order == 4:
+        Rc = R_of_state_point(fourth_order.to_centres(U, prob.dim), prob)
+        return fourth_order.to_averages(Rc, prob.dim)
+    return R_of_state_point(U, prob)
+
+
+def R_of_state_point(U, prob: Problem):
     rho, _, x, _ = split_state(U, prob)
     return R_full_from_x(R_of_x(x, rho, prob), prob)
 
@@ -206,14 +230,22 @@ def sweep(Un, A, R, U, dt, prob: Problem, stats: Stats | None = None):
             A_new.append(Am)
         integral = dt * sum(S[m, j] * (A[j] + R[j]) for j in range(M + 1))
         rhs = U_new[m] + dtm * (Am - A[m]) - dtm * R[m + 1] + integral
-        rho, mom, b, ke = split_state(rhs, prob)
-        # b currently holds (rhs_rhoX, rhs_rhoE - KE_new): the reacting rhs
         _, _, x0, _ = split_state(U[m + 1], prob)
-        x, nu = newton_solve(b, rho, dtm, x0, prob)
+        if prob.space_order == 4:
+            # the solve at zone centres, the source back to a zone average
+            rho, _, b, _ = split_state(fourth_order.to_centres(rhs, prob.dim), prob)
+            x, nu = newton_solve(b, rho, dtm, x0, prob)
+            Ravg = fourth_order.to_averages(R_full_from_x(R_of_x(x, rho, prob), prob), prob.dim)
+            U_new.append(rhs + dtm * Ravg)
+            R_new.append(Ravg)
+        else:
+            rho, mom, b, ke = split_state(rhs, prob)
+            # b holds (rhs_rhoX, rhs_rhoE - KE_new): the reacting rhs
+            x, nu = newton_solve(b, rho, dtm, x0, prob)
+            U_new.append(join_state(rho, mom, x, ke, prob))
+            R_new.append(R_full_from_x(R_of_x(x, rho, prob), prob))
         if stats is not None:
             stats.add(nu)
-        U_new.append(join_state(rho, mom, x, ke, prob))
-        R_new.append(R_full_from_x(R_of_x(x, rho, prob), prob))
     A_new.append(A_of(U_new[M], prob))
     return U_new, A_new, R_new
 
