@@ -182,6 +182,28 @@ int sdc_reaction_solve(sdc_handle h, double dt_m, const double* rho, const doubl
                        double* R, int32_t* iters, void* stream);
 
 /*
+ * sdc_reaction_solve for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, on `nzones` zones of arrays laid
+ * out [component][nzones] (rho: [nzones]; b, x, R: [n_r][nzones]; iters:
+ * int32 [nzones]), independent of the handle's grid size.  Its deferred-zone
+ * queue lives in a fixed device array of SDC_NOALLOC_SCRATCH_BYTES inside the
+ * library (one per device, held until the process ends), so the call makes no
+ * hipMalloc, hipFree or other allocation and records no profiling events.
+ * Limit: the queue needs 24 + 16 n_r bytes per zone (plus at most 2 KiB of
+ * alignment), about 270,000 zones at n_r = 14; a larger nzones returns
+ * SDC_ERR_ARG (the message gives the limit).  nzones = 0 is a no-op.  Calls that overlap on
+ * one device (concurrent streams, or handles on several threads) share that
+ * device's array and race; calls serialised on one stream do not.  The queue
+ * counter is cleared by a kernel at the start of each call.  Errors as
+ * sdc_reaction_solve, plus SDC_ERR_HIP if the array's address could not be
+ * resolved when the handle was created.
+ */
+#define SDC_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int sdc_reaction_solve_noalloc(sdc_handle h, double dt_m, int64_t nzones, const double* rho, const double* b,
+                               double* x, double* R, int32_t* iters, void* stream);
+
+/*
  * One SDC iteration k -> k+1 over the transitions m = 0..M-1 of Eq. 2 for a
  * step of length dt, followed by A at the last node.  On entry nodes->U[0],
  * A[0], R[0] hold U^n, A(U^n), R(U^n); for k >= 1 the other nodes hold

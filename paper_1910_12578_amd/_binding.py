@@ -24,7 +24,8 @@ EXPORTS = ("sdc_config_default", "sdc_init", "sdc_destroy", "sdc_last_error", "s
            "sdc_advective_term", "sdc_source", "sdc_reaction_solve", "sdc_sweep", "sdc_step",
            "sdc_stats", "sdc_check", "sdc_stats_reset", "sdc_set_params", "sdc_compile_only",
            "sdc_generated_source", "sdc_aot_name", "sdc_profile_enable", "sdc_profile_read", "sdc_cost_model",
-           "sdc_step_adjoint", "sdc_set_schedule", "sdc_get_schedule", "sdc_autotune")
+           "sdc_step_adjoint", "sdc_set_schedule", "sdc_get_schedule", "sdc_autotune",
+           "sdc_reaction_solve_noalloc")
 KINDS = ("advect", "source", "solve", "transition_first", "transition_node0", "transition_later", "fill",
          "adjoint", "finish", "split")
 
@@ -78,6 +79,8 @@ def lib():
         L.sdc_source.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
         L.sdc_reaction_solve.argtypes = [c_void_p, c_double, c_void_p, c_void_p, c_void_p, c_void_p,
                                          c_void_p, c_void_p]
+        L.sdc_reaction_solve_noalloc.argtypes = [c_void_p, c_double, c_int64, c_void_p, c_void_p, c_void_p,
+                                                 c_void_p, c_void_p, c_void_p]
         L.sdc_sweep.argtypes = [c_void_p, c_double, c_int32, POINTER(Nodes), c_void_p]
         L.sdc_step.argtypes = [c_void_p, c_double, c_int32, c_void_p, POINTER(Nodes), c_void_p]
         L.sdc_stats.argtypes = [c_void_p, POINTER(c_int64)]
@@ -272,6 +275,24 @@ class SDC:
         _check(lib().sdc_reaction_solve(self._h, float(dtm), self._ptr(rho, 1), self._ptr(b, self.nreact_vars),
                                         self._ptr(x, self.nreact_vars), self._ptr(R, self.nreact_vars),
                                         self._ptr(iters, 1, torch.int32), self._stream(stream)), self._h)
+        return x, R, iters
+
+    def reaction_solve_noalloc(self, dtm, rho, b, x, R, iters, stream=None):
+        """sdc_reaction_solve_noalloc on the zones of `rho` ([nz]); b, x, R:
+        [n_r][nz], iters: int32 [nz], all preallocated by the caller."""
+        import torch
+        nz = rho.numel()
+        for t, nc, dt in ((rho, 1, torch.float64), (b, self.nreact_vars, torch.float64),
+                          (x, self.nreact_vars, torch.float64), (R, self.nreact_vars, torch.float64),
+                          (iters, 1, torch.int32)):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+                raise TypeError(f"expected a contiguous CUDA tensor of {dt}")
+            if t.numel() != nc * nz:
+                raise ValueError(f"expected {nc} x {nz} elements, got {tuple(t.shape)}")
+        _check(lib().sdc_reaction_solve_noalloc(self._h, float(dtm), nz, c_void_p(rho.data_ptr()),
+                                                c_void_p(b.data_ptr()), c_void_p(x.data_ptr()),
+                                                c_void_p(R.data_ptr()), c_void_p(iters.data_ptr()),
+                                                self._stream(stream)), self._h)
         return x, R, iters
 
     def alloc_nodes(self):

@@ -28,9 +28,60 @@
 // kSdcArgsSrc, kSdcDeviceSrc: the kernel sources as string literals
 #include "_gen/sdc_device_src.inc"
 
+// Scratch memory of sdc_reaction_solve_noalloc: its deferred-zone queue lives
+// in this array of the library's own code object, one copy per device, held
+// until the process ends.  In host code the name is only a stand-in for the
+// device array: host code resolves the address once per device with
+// hipGetSymbolAddress (scratch_address below) and uses that pointer only.
+static __device__ __align__(256) unsigned char scratch[SDC_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_init_error;
+
+// Device address of `scratch` per device, resolved once with that device
+// current (each device holds its own copy of the array at its own address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_rc[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// Resolve the scratch array of the current device `dev`; returns its address
+// or nullptr (then *rc holds the HIP error).
+void* scratch_address(int dev, hipError_t* rc) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    *rc = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_done[dev]) {
+    void* p = nullptr;
+    g_scratch_rc[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_ptr[dev] = g_scratch_rc[dev] == hipSuccess ? p : nullptr;
+    g_scratch_done[dev] = true;
+  }
+  *rc = g_scratch_rc[dev];
+  return g_scratch_ptr[dev];
+}
+
+// Deferred-zone queue of `cap` zones carved from a scratch block of `bytes`
+// (256-byte aligned pieces: counter, zone index, iteration, x, b, rho).
+// Returns the bytes used, or -1 if they exceed `bytes`.
+int64_t carve_queue(unsigned char* base, int64_t bytes, int64_t cap, int nx, DeferQueue* q) {
+  auto up = [](int64_t v) { return (v + 255) & ~int64_t(255); };
+  const int64_t o_z = 256, o_it = o_z + up(cap * 8), o_x = o_it + up(cap * 4), o_b = o_x + up(cap * 8 * nx),
+                o_aux = o_b + up(cap * 8 * nx), end = o_aux + up(cap * 8);
+  if (end > bytes) return -1;
+  q->count = (unsigned*)base;
+  q->z = (sdc_i64*)(base + o_z);
+  q->it = (int*)(base + o_it);
+  q->x = (double*)(base + o_x);
+  q->b = (double*)(base + o_b);
+  q->aux = (double*)(base + o_aux);
+  q->capacity = cap;
+  return end;
+}
 
 constexpr int kBlock = 256;
 // Grid of the deferred-zone finish kernels, which stride over the queue: an
@@ -411,6 +462,10 @@ struct sdc_handle_s {
   int row_bw = 256;  // threads per block of the row kernel (512 for rows of 257..512 zones)
   int zchunk = 0;  // row kernel tile: planes per z chunk (0: heuristic)
   hipStream_t last_stream = nullptr;
+  // device of the handle's module and its scratch array (noalloc entry point)
+  int device = 0;
+  void* scratch = nullptr;
+  hipError_t scratch_rc = hipSuccess;
   std::string err;
   // per-kernel timing
   bool profile = false;
@@ -1241,7 +1296,10 @@ int sdc_init(const sdc_config* cfg, const sdc_network* net, sdc_handle* out) {
     sdc_destroy(h);
     return fail(nullptr, code_, msg);
   };
-  hipError_t e = hipModuleLoadData(&h->mod, code.data());
+  hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) return bail(SDC_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  h->scratch = scratch_address(h->device, &h->scratch_rc);
+  e = hipModuleLoadData(&h->mod, code.data());
   if (e != hipSuccess) return bail(SDC_ERR_HIP, std::string("hipModuleLoadData: ") + hipGetErrorString(e));
   struct {
     hipFunction_t* f;
@@ -1386,6 +1444,50 @@ int sdc_reaction_solve(sdc_handle h, double dt_m, const double* rho, const doubl
   if (int rc = reset_queue(h, s)) return rc;
   if (int rc = launch(h, h->occ2 ? h->f_solve_o2 : h->f_solve, h->P.Z, &a, s)) return rc;
   return launch(h, h->f_solve_finish, std::min<int64_t>(h->P.Z, kFinishThreads), &a, s);
+}
+
+int sdc_reaction_solve_noalloc(sdc_handle h, double dt_m, int64_t nzones, const double* rho, const double* b,
+                               double* x, double* R, int32_t* iters, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (nzones < 0) return fail(h, SDC_ERR_ARG, "nzones must be >= 0");
+  if (nzones == 0) return SDC_OK;
+  if (!rho || !b || !x || !R || !iters) return fail(h, SDC_ERR_ARG, "null array");
+  if (!std::isfinite(dt_m) || dt_m < 0.0) return fail(h, SDC_ERR_ARG, "dt_m must be finite and >= 0");
+  if ((const double*)x == b) return fail(h, SDC_ERR_ARG, "x and b must not alias");
+  if (!h->scratch)
+    return fail(h, SDC_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(h->scratch_rc));
+  SolveArgs a;
+  std::memset(&a, 0, sizeof a);
+  if (carve_queue((unsigned char*)h->scratch, SDC_NOALLOC_SCRATCH_BYTES, nzones, h->nx, &a.q) < 0) {
+    const int64_t per = 8 + 4 + 16 * (int64_t)h->nx + 8;
+    return fail(h, SDC_ERR_ARG, "nzones = " + std::to_string(nzones) + " exceeds the scratch array of " +
+                                    std::to_string((long long)SDC_NOALLOC_SCRATCH_BYTES) + " bytes (about " +
+                                    std::to_string((SDC_NOALLOC_SCRATCH_BYTES - 2048) / per) + " zones at " +
+                                    std::to_string(h->nx) + " reacting components)");
+  }
+  h->last_stream = (hipStream_t)stream;
+  a.Z = nzones;
+  a.dtm = dt_m;
+  a.rho = rho;
+  a.b = b;
+  a.x = x;
+  a.R = R;
+  a.iters = iters;
+  a.P = h->d_params;
+  a.gm1 = h->P.cfg.gamma - 1.0;
+  a.ctl = newton_ctl(h);
+  a.stats = h->d_stats;
+  // plain launches: no profiling events, no allocation of any kind
+  hipStream_t s = (hipStream_t)stream;
+  void* reset_params[] = {&a.q.count};
+  HIP_CHECK(h, hipModuleLaunchKernel(h->f_reset, 1, 1, 1, 64, 1, 1, 0, s, reset_params, nullptr));
+  void* params[] = {&a};
+  const unsigned nb = (unsigned)((nzones + kBlock - 1) / kBlock);
+  HIP_CHECK(h, hipModuleLaunchKernel(h->occ2 ? h->f_solve_o2 : h->f_solve, nb, 1, 1, kBlock, 1, 1, 0, s, params,
+                                     nullptr));
+  const unsigned nf = (unsigned)((std::min<int64_t>(nzones, kFinishThreads) + kBlock - 1) / kBlock);
+  HIP_CHECK(h, hipModuleLaunchKernel(h->f_solve_finish, nf, 1, 1, kBlock, 1, 1, 0, s, params, nullptr));
+  return SDC_OK;
 }
 
 int sdc_sweep(sdc_handle h, double dt, int32_t k, const sdc_nodes* nodes, void* stream) {
