@@ -56,7 +56,9 @@ extern "C" {
 #define SDC_FP64 0  /* every step in float64 */
 #define SDC_MIXED 1 /* Newton matrix and LU in float32; residual, update, quadrature in float64 */
 
-#define SDC_MAX_NODES 5  /* Gauss-Lobatto nodes per step: 2..5 */
+#define SDC_MAX_NODES 5  /* temporal nodes per step: 2..5 */
+#define SDC_NODES_LOBATTO 0
+#define SDC_NODES_RADAU 1
 #define SDC_MAX_SPECIES 31
 
 /* counters returned by sdc_stats */
@@ -96,7 +98,7 @@ typedef struct {
   int64_t n[3];            /* zones per direction (x, y, z); entries beyond dim ignored */
   double dx[3];            /* zone widths; the grid is periodic in every direction */
   double gamma;            /* gamma-law EOS, p = (gamma - 1) rho e, code units p = rho T */
-  int32_t n_nodes;         /* Gauss-Lobatto nodes per step (2 = trapezoid, 3 = Simpson, .. 5) */
+  int32_t n_nodes;         /* temporal nodes per step, 2..5 (Gauss-Lobatto: 2 = trapezoid, 3 = Simpson) */
   int32_t n_iters;         /* SDC iterations K per step, >= 1 */
   int32_t precision;       /* SDC_FP64 or SDC_MIXED */
   int32_t advection;       /* 0: A == 0 (reaction only), 1: advective term on */
@@ -119,6 +121,23 @@ typedef struct {
    * kernel source and size, or runs sdc_autotune on its input; 0 (default):
    * the schedule set with sdc_set_schedule (initially 0, 0, 0, 0). */
   int32_t autotune;
+  /* Temporal nodes of a step (n_nodes of them, tau_0 = 0 and tau_M = 1):
+   * SDC_NODES_LOBATTO (default): Gauss-Lobatto points, the node-to-node
+   * integrals interpolate through every node (trapezoid and Simpson for 2 and
+   * 3 nodes, Sec. 2); SDC_NODES_RADAU: tau_0 = 0 followed by the n_nodes - 1
+   * right Radau points, the integrals interpolate through the Radau points
+   * only, so the sweeps converge to Radau IIA collocation, which damps very
+   * stiff modes (the quadratures for highly stiff reactions of Sec. 5). */
+  int32_t node_type;
+  /* Spatial order of the finite-volume terms: 2 (default; PLM + Rusanov as
+   * above, zone-local sources) or 4, the paper's fourth-order method (Sec. 2:
+   * Simpson in time with McCorquodale and Colella's reconstruction): A from
+   * fourth-order face averages, face-centre values and face-averaged fluxes
+   * (no limiter, so slope and alpha are ignored; for smooth flows), and the
+   * reactive terms as zone averages of R at zone-centre states, the Newton
+   * solve of each transition running on the zone-centre values of its
+   * right-hand side.  Single grids only (nbox = 0); no adjoint. */
+  int32_t space_order;
 } sdc_config;
 
 /*
@@ -297,7 +316,8 @@ int sdc_autotune(sdc_handle h, double dt, const double* U, const sdc_nodes* work
 #define SDC_K_ADJOINT 7  /* every kernel of the adjoint pass */
 #define SDC_K_FINISH 8   /* second-stage kernels of capped or guarded Newton solves */
 #define SDC_K_SPLIT 9    /* batch kernels of the split schedule (each transition is also timed as one span) */
-#define SDC_NKINDS 10
+#define SDC_K_ORDER4 10  /* centre conversions and average stores of fourth-order transitions */
+#define SDC_NKINDS 11
 
 /*
  * Per-kernel timing: while enabled, every launch is bracketed by HIP events

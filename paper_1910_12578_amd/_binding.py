@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsdc.so")
 
 SDC_FP64, SDC_MIXED = 0, 1
+NODE_TYPES = {"lobatto": 0, "radau": 1}
 MAX_NODES = 5
 NSTATS = 21
 ERRORS = {1: "SDC_ERR_ARG", 2: "SDC_ERR_HIP", 3: "SDC_ERR_NOMEM", 4: "SDC_ERR_NEWTON",
@@ -27,7 +28,7 @@ EXPORTS = ("sdc_config_default", "sdc_init", "sdc_destroy", "sdc_last_error", "s
            "sdc_step_adjoint", "sdc_set_schedule", "sdc_get_schedule", "sdc_autotune",
            "sdc_reaction_solve_noalloc")
 KINDS = ("advect", "source", "solve", "transition_first", "transition_node0", "transition_later", "fill",
-         "adjoint", "finish", "split")
+         "adjoint", "finish", "split", "order4")
 
 
 class SDCError(RuntimeError):
@@ -48,7 +49,8 @@ class Config(ctypes.Structure):
                 ("advection", c_int32), ("slope", c_int32), ("alpha", c_double),
                 ("newton_tol", c_double), ("newton_maxiter", c_int32),
                 ("pivot_threshold", c_double), ("nbox", c_int32), ("box_n", POINTER(c_int64)),
-                ("graph", c_int32), ("autotune", c_int32)]
+                ("graph", c_int32), ("autotune", c_int32), ("node_type", c_int32),
+                ("space_order", c_int32)]
 
 
 class Nodes(ctypes.Structure):
@@ -142,7 +144,10 @@ def make_config(cfg):
     for key in ("gamma", "alpha", "newton_tol", "pivot_threshold"):
         if key in cfg:
             setattr(c, key, float(cfg[key]))
-    for key in ("n_nodes", "n_iters", "precision", "advection", "slope", "newton_maxiter", "graph", "autotune"):
+    if "node_type" in cfg:
+        c.node_type = NODE_TYPES[cfg["node_type"]] if isinstance(cfg["node_type"], str) else int(cfg["node_type"])
+    for key in ("n_nodes", "n_iters", "precision", "advection", "slope", "newton_maxiter", "graph", "autotune",
+                "space_order"):
         if key in cfg:
             setattr(c, key, int(cfg[key]))
     return c
@@ -153,7 +158,8 @@ def config_from_workload(w, **over):
     cfg = dict(dim=w["dim"], n=tuple(w["shape"] or ()), dx=tuple(w["dx"]), gamma=w["gamma"],
                n_nodes=w["n_nodes"], n_iters=w["n_iters"], precision=SDC_FP64, advection=1,
                slope=w["slope"], alpha=w["alpha"], newton_tol=w["newton_tol"],
-               newton_maxiter=w["newton_maxiter"])
+               newton_maxiter=w["newton_maxiter"], node_type=w.get("node_type", "lobatto"),
+               space_order=w.get("space_order", 2))
     if w.get("box_n") is not None:
         cfg["box_n"] = w["box_n"]
     cfg.update(over)

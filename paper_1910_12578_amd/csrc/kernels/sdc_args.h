@@ -101,7 +101,50 @@ typedef struct {
   // batch [zbeg, zbeg + zcount); `split` holds [NX + 2][Z]: b, KE, x_e guess
   double* split;
   sdc_i64 zbeg, zcount;
+  // fourth-order right-hand-side kernels: the rhs is written to Uout and the
+  // Newton guess (reacting vector of U^{m+1,(k)}) to x4 [NX][Z]
+  double* x4;
 } TransArgs;
+
+// Fourth-order finite volume, zone-per-thread stencil kernels on a periodic
+// grid (x fastest).  Face-averaged flux through the face at i+1/2 along `d`
+// (flux kernels), its divergence accumulated into A (first: A = -div,
+// otherwise A -= div), and the conversions between zone averages and zone
+// centres (sign -1: centres from averages, +1: averages from centres) of
+// `ncomp` components.
+typedef struct {
+  const double* U;
+  double* F;
+  double* A;
+  sdc_i64 Z;
+  int n[3];
+  int first;
+  double idx;
+  double gamma;
+} Flux4Args;
+
+typedef struct {
+  const double* src;
+  double* dst;
+  sdc_i64 Z;
+  int n[3];
+  int ncomp;
+  double sign;
+} ConvArgs;
+
+// Fourth-order transition pieces around the zone-centre Newton solve.
+typedef struct {
+  sdc_i64 Z;
+  int n[3];
+  double dtm;
+  double* U;          // [NC][Z] the node's output: the rhs, then U^{m+1} = rhs + dt_m <R>
+  double* R;          // [NX][Z] <R>^{m+1}
+  double* rho_c;      // [Z] zone-centre density of the rhs
+  double* b_c;        // [NX][Z] zone-centre reacting rhs
+  const double* R_c;  // [NX][Z] R at the zone-centre root
+  const void* P;      // NetParams (source kernel)
+  double gm1;
+} O4Args;
 
 typedef struct {
   double* p;

@@ -877,6 +877,47 @@ __device__ __forceinline__ void transition_store(const TransArgs& a, i64 z, doub
   for (int i = 0; i < SDC_NX; ++i) st_s(&a.Rout[(i64)i * Z + z], R[i]);
 }
 
+// Right-hand side of Eq. 2 for zone z (all components), with the quadrature
+// of every node and the C_m outputs for m = 0.
+template <int KIND>
+__device__ __forceinline__ void transition_rhs(const TransArgs& a, i64 z, double* rhs) {
+  const i64 Z = a.Z;
+  if (KIND == KIND_FIRST) {
+#pragma unroll
+    for (int c = 0; c < SDC_NC; ++c) rhs[c] = fma(a.dtm, ld_s(&a.Am[(i64)c * Z + z]), ld_s(&a.Um[(i64)c * Z + z]));
+  } else if (KIND == KIND_NODE0) {
+#pragma unroll
+    for (int c = 0; c < SDC_NC; ++c) {
+      const int ri = c == 1 + SDC_DIM ? SDC_NX - 1 : (c >= SDC_NH ? c - SDC_NH : -1);
+      double f[SDC_NNODES];
+#pragma unroll
+      for (int j = 0; j <= SDC_M; ++j) {
+        f[j] = ld_s(&a.Aold[j][(i64)c * Z + z]);
+        if (ri >= 0) f[j] += ld_s(&a.Rold[j][(i64)ri * Z + z]);
+      }
+      double i0 = 0.0;
+#pragma unroll
+      for (int j = 0; j <= SDC_M; ++j) i0 = fma(a.S[0][j], f[j], i0);
+      double r = fma(a.dt, i0, ld_s(&a.Um[(i64)c * Z + z]));
+      if (ri >= 0) r = fma(-a.dtm, ld_s(&a.Rold[1][(i64)ri * Z + z]), r);
+      rhs[c] = r;
+#pragma unroll
+      for (int mm = 1; mm < SDC_M; ++mm) {
+        double im = 0.0;
+#pragma unroll
+        for (int j = 0; j <= SDC_M; ++j) im = fma(a.S[mm][j], f[j], im);
+        double cm = fma(-a.dtj[mm], ld_s(&a.Aold[mm][(i64)c * Z + z]), a.dt * im);
+        if (ri >= 0) cm = fma(-a.dtj[mm], ld_s(&a.Rold[mm + 1][(i64)ri * Z + z]), cm);
+        st_s(&a.Cout[mm - 1][(i64)c * Z + z], cm);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < SDC_NC; ++c)
+      rhs[c] = fma(a.dtm, ld_s(&a.Am[(i64)c * Z + z]), ld_s(&a.Um[(i64)c * Z + z])) + ld_s(&a.Cin[(i64)c * Z + z]);
+  }
+}
+
 // Explicit part of the transition of zone z: the right-hand side of Eq. 2
 // (with the quadrature of every node and the C_m outputs for m = 0), the final
 // rho and rho u, KE at m+1, the reacting right-hand side b and the energy
@@ -887,40 +928,7 @@ __device__ __forceinline__ void transition_explicit(const TransArgs& a, i64 z, d
   const i64 Z = a.Z;
   {
     double rhs[SDC_NC];
-    if (KIND == KIND_FIRST) {
-#pragma unroll
-      for (int c = 0; c < SDC_NC; ++c) rhs[c] = fma(a.dtm, ld_s(&a.Am[(i64)c * Z + z]), ld_s(&a.Um[(i64)c * Z + z]));
-    } else if (KIND == KIND_NODE0) {
-#pragma unroll
-      for (int c = 0; c < SDC_NC; ++c) {
-        const int ri = c == 1 + SDC_DIM ? SDC_NX - 1 : (c >= SDC_NH ? c - SDC_NH : -1);
-        double f[SDC_NNODES];
-#pragma unroll
-        for (int j = 0; j <= SDC_M; ++j) {
-          f[j] = ld_s(&a.Aold[j][(i64)c * Z + z]);
-          if (ri >= 0) f[j] += ld_s(&a.Rold[j][(i64)ri * Z + z]);
-        }
-        double i0 = 0.0;
-#pragma unroll
-        for (int j = 0; j <= SDC_M; ++j) i0 = fma(a.S[0][j], f[j], i0);
-        double r = fma(a.dt, i0, ld_s(&a.Um[(i64)c * Z + z]));
-        if (ri >= 0) r = fma(-a.dtm, ld_s(&a.Rold[1][(i64)ri * Z + z]), r);
-        rhs[c] = r;
-#pragma unroll
-        for (int mm = 1; mm < SDC_M; ++mm) {
-          double im = 0.0;
-#pragma unroll
-          for (int j = 0; j <= SDC_M; ++j) im = fma(a.S[mm][j], f[j], im);
-          double cm = fma(-a.dtj[mm], ld_s(&a.Aold[mm][(i64)c * Z + z]), a.dt * im);
-          if (ri >= 0) cm = fma(-a.dtj[mm], ld_s(&a.Rold[mm + 1][(i64)ri * Z + z]), cm);
-          st_s(&a.Cout[mm - 1][(i64)c * Z + z], cm);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < SDC_NC; ++c)
-        rhs[c] = fma(a.dtm, ld_s(&a.Am[(i64)c * Z + z]), ld_s(&a.Um[(i64)c * Z + z])) + ld_s(&a.Cin[(i64)c * Z + z]);
-    }
+    transition_rhs<KIND>(a, z, rhs);
     // explicit part: rho and rho u are final
     rho = rhs[0];
     ke = 0.0;
@@ -1125,6 +1133,281 @@ extern "C" __global__ __launch_bounds__(256) SDC_OCC2 void sdc_transition_later_
 extern "C" __global__ __launch_bounds__(256) void sdc_transition_finish(TransArgs a) { transition_finish_body<SdcMT>(a); }
 
 // reset of the deferred-zone counter (a kernel, so captured graphs stay valid)
+// ------------------------------------------------------------ fourth order
+// The fourth-order method in space (Sec. 2: Simpson in time with McCorquodale
+// and Colella's reconstruction), on zone averages of a periodic grid:
+//  - face average along d of the face at i+1/2: 7/12 (u_i + u_{i+1})
+//    - 1/12 (u_{i-1} + u_{i+2});
+//  - face-centre value: face average minus 1/24 of its second differences
+//    across the face (the other directions); the flux at the face centre is
+//    the Euler flux of that value, and the face-averaged flux adds 1/24 of the
+//    second differences across the face of the flux of the face averages;
+//  - no limiter: both face states coincide, the Rusanov term vanishes;
+//  - zone centres u_c = <u> - lap/24 and zone averages <f> = f_c + lap/24,
+//    lap the sum over directions of second differences.
+// Zone-per-thread kernels: stencil values come through L1/L2.
+
+__device__ __forceinline__ void zone_coords(i64 z, const int* n, int* c) {
+  const i64 plane = (i64)n[0] * n[1];
+  c[2] = (int)(z / plane);
+  const i64 r = z - (i64)c[2] * plane;
+  c[1] = (int)(r / n[0]);
+  c[0] = (int)(r - (i64)c[1] * n[0]);
+}
+
+// zone (c + o0 e_d0 + o1 e_d1), periodic, for offsets of any size
+__device__ __forceinline__ i64 zone_off(const int* c, const int* n, int d0, int o0, int d1, int o1) {
+  int q[3] = {c[0], c[1], c[2]};
+  q[d0] += o0;
+  q[d1] += o1;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    q[e] %= n[e];
+    if (q[e] < 0) q[e] += n[e];
+  }
+  return (i64)q[0] + (i64)n[0] * ((i64)q[1] + (i64)n[1] * q[2]);
+}
+
+// second differences of u summed over directions: sum_d (u_{+d} - 2 u) + u_{-d}
+__device__ __forceinline__ double lap_sum(const double* u, const int* c, const int* n, double u0) {
+  double l = 0.0;
+#pragma unroll
+  for (int d = 0; d < SDC_DIM; ++d) l += (u[zone_off(c, n, d, 1, d, 0)] - 2.0 * u0) + u[zone_off(c, n, d, -1, d, 0)];
+  return l;
+}
+
+// Transverse positions of a face normal to D: the face itself, then +/- one
+// zone along every other direction, in increasing direction order.
+#define SDC_NT (2 * SDC_DIM - 1)
+template <int D>
+__device__ __forceinline__ void transverse(int t, int& dd, int& o) {
+  // t = 0: the face; t = 1 + 2 j (+) and 2 + 2 j (-) for the j-th other direction
+  dd = D;
+  o = 0;
+  if (t > 0) {
+    const int j = (t - 1) >> 1;
+    dd = j < D ? j : j + 1;
+    o = (t & 1) ? 1 : -1;
+  }
+}
+
+// face average along D at the face i+1/2 of the zone c shifted by o along dd
+template <int D>
+__device__ __forceinline__ double face_avg4(const double* u, const int* c, const int* n, int dd, int o) {
+  const double a = u[zone_off(c, n, dd, o, D, 0)], b = u[zone_off(c, n, dd, o, D, 1)];
+  const double am = u[zone_off(c, n, dd, o, D, -1)], bp = u[zone_off(c, n, dd, o, D, 2)];
+  return (7.0 / 12.0) * (a + b) - (1.0 / 12.0) * (am + bp);
+}
+
+// 1/24 of the second differences across the face from the face values v[t]
+__device__ __forceinline__ double cross_lap24(const double* v) {
+  double l = 0.0;
+#pragma unroll
+  for (int j = 0; j < SDC_DIM - 1; ++j) l += (v[1 + 2 * j] - 2.0 * v[0]) + v[2 + 2 * j];
+  return l / 24.0;
+}
+
+template <int D>
+__device__ __forceinline__ void flux4_body(const Flux4Args& a) {
+  const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= a.Z) return;
+  const i64 Z = a.Z;
+  int c[3];
+  zone_coords(z, a.n, c);
+  // hydro components: face averages at the transverse positions, their
+  // fluxes and velocities, the face-centre value and its flux
+  double W[SDC_NT][SDC_NH], un[SDC_NT];
+  double F[SDC_NH], Fc[SDC_NH], Wc[SDC_NH], unc, p, cs;
+#pragma unroll
+  for (int t = 0; t < SDC_NT; ++t) {
+    int dd, o;
+    transverse<D>(t, dd, o);
+#pragma unroll
+    for (int q = 0; q < SDC_NH; ++q) W[t][q] = face_avg4<D>(a.U + (i64)q * Z, c, a.n, dd, o);
+  }
+#pragma unroll
+  for (int q = 0; q < SDC_NH; ++q) {
+    double v[SDC_NT];
+#pragma unroll
+    for (int t = 0; t < SDC_NT; ++t) v[t] = W[t][q];
+    Wc[q] = W[0][q] - cross_lap24(v);
+  }
+  hydro_flux(Wc, D, a.gamma, Fc, unc, p, cs);
+  {
+    double Ft[SDC_NT][SDC_NH];
+#pragma unroll
+    for (int t = 0; t < SDC_NT; ++t) hydro_flux(W[t], D, a.gamma, Ft[t], un[t], p, cs);
+#pragma unroll
+    for (int q = 0; q < SDC_NH; ++q) {
+      double v[SDC_NT];
+#pragma unroll
+      for (int t = 0; t < SDC_NT; ++t) v[t] = Ft[t][q];
+      F[q] = Fc[q] + cross_lap24(v);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < SDC_NH; ++q) a.F[(i64)q * Z + z] = F[q];
+  // species: passive, flux u_n times the species density
+  for (int s = 0; s < SDC_NS; ++s) {
+    const double* us = a.U + (i64)(SDC_NH + s) * Z;
+    double v[SDC_NT], f[SDC_NT];
+#pragma unroll
+    for (int t = 0; t < SDC_NT; ++t) {
+      int dd, o;
+      transverse<D>(t, dd, o);
+      v[t] = face_avg4<D>(us, c, a.n, dd, o);
+      f[t] = v[t] * un[t];
+    }
+    const double vc = v[0] - cross_lap24(v);
+    a.F[(i64)(SDC_NH + s) * Z + z] = vc * unc + cross_lap24(f);
+  }
+}
+
+extern "C" __global__ __launch_bounds__(256) void sdc_flux4_0(Flux4Args a) { flux4_body<0>(a); }
+#if SDC_DIM >= 2
+extern "C" __global__ __launch_bounds__(256) void sdc_flux4_1(Flux4Args a) { flux4_body<1>(a); }
+#endif
+#if SDC_DIM >= 3
+extern "C" __global__ __launch_bounds__(256) void sdc_flux4_2(Flux4Args a) { flux4_body<2>(a); }
+#endif
+
+// A (=, or -=) (F_{i+1/2} - F_{i-1/2}) / dx_d for the face fluxes F along d
+template <int D>
+__device__ __forceinline__ void div4_body(const Flux4Args& a) {
+  const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= a.Z) return;
+  const i64 Z = a.Z;
+  int c[3];
+  zone_coords(z, a.n, c);
+  const i64 zm = zone_off(c, a.n, D, -1, D, 0);
+  for (int q = 0; q < SDC_NC; ++q) {
+    const double dv = (a.F[(i64)q * Z + z] - a.F[(i64)q * Z + zm]) * a.idx;
+    a.A[(i64)q * Z + z] = (a.first ? 0.0 : a.A[(i64)q * Z + z]) - dv;
+  }
+}
+extern "C" __global__ __launch_bounds__(256) void sdc_div4_0(Flux4Args a) { div4_body<0>(a); }
+#if SDC_DIM >= 2
+extern "C" __global__ __launch_bounds__(256) void sdc_div4_1(Flux4Args a) { div4_body<1>(a); }
+#endif
+#if SDC_DIM >= 3
+extern "C" __global__ __launch_bounds__(256) void sdc_div4_2(Flux4Args a) { div4_body<2>(a); }
+#endif
+
+// dst = src + sign * lap / 24 on ncomp components (src and dst distinct)
+extern "C" __global__ __launch_bounds__(256) void sdc_convert4(ConvArgs a) {
+  const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= a.Z) return;
+  int c[3];
+  zone_coords(z, a.n, c);
+  for (int q = 0; q < a.ncomp; ++q) {
+    const double* u = a.src + (i64)q * a.Z;
+    const double u0 = u[z];
+    a.dst[(i64)q * a.Z + z] = u0 + a.sign * (lap_sum(u, c, a.n, u0) / 24.0);
+  }
+}
+
+// R at the zone-centre values of U, into R [NX][Z]
+extern "C" __global__ __launch_bounds__(256) void sdc_source4_centre(O4Args a) {
+  ParamPtr P = stage_params(a.P);
+  const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= a.Z) return;
+  const i64 Z = a.Z;
+  int c[3];
+  zone_coords(z, a.n, c);
+  double uc[SDC_NC];
+  for (int q = 0; q < SDC_NC; ++q) {
+    const double* u = a.U + (i64)q * Z;
+    const double u0 = u[z];
+    uc[q] = u0 - lap_sum(u, c, a.n, u0) / 24.0;
+  }
+  double ke = 0.0;
+#pragma unroll
+  for (int d = 0; d < SDC_DIM; ++d) ke = fma(uc[1 + d], uc[1 + d], ke);
+  ke = 0.5 * ke / uc[0];
+  double x[SDC_NX], R[SDC_NX];
+#pragma unroll
+  for (int s = 0; s < SDC_NS; ++s) x[s] = uc[SDC_NH + s];
+  x[SDC_NX - 1] = uc[1 + SDC_DIM] - ke;
+  net_source(x, 1.0 / uc[0], P, a.gm1, R);
+#pragma unroll
+  for (int i = 0; i < SDC_NX; ++i) a.R[(i64)i * Z + z] = R[i];
+}
+
+// Right-hand side of the transition into Uout (zone averages) and the Newton
+// guess into x4; the guess is read before Uout is written (they may share
+// the node array).
+template <int KIND>
+__device__ __forceinline__ void rhs4_body(const TransArgs& a) {
+  const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= a.Z) return;
+  const i64 Z = a.Z;
+  double rhs[SDC_NC];
+  transition_rhs<KIND>(a, z, rhs);
+  {
+    const double* __restrict__ g = a.guess;
+    const double grho = g[z];
+    double gke = 0.0;
+#pragma unroll
+    for (int d = 0; d < SDC_DIM; ++d) {
+      const double mo = g[(i64)(1 + d) * Z + z];
+      gke = fma(mo, mo, gke);
+    }
+    gke = 0.5 * gke / grho;
+    double xg[SDC_NX];
+#pragma unroll
+    for (int s = 0; s < SDC_NS; ++s) xg[s] = g[(i64)(SDC_NH + s) * Z + z];
+    xg[SDC_NX - 1] = g[(i64)(1 + SDC_DIM) * Z + z] - gke;
+#pragma unroll
+    for (int i = 0; i < SDC_NX; ++i) a.x4[(i64)i * Z + z] = xg[i];
+  }
+#pragma unroll
+  for (int q = 0; q < SDC_NC; ++q) a.Uout[(i64)q * Z + z] = rhs[q];
+}
+extern "C" __global__ __launch_bounds__(256) void sdc_rhs4_first(TransArgs a) { rhs4_body<KIND_FIRST>(a); }
+extern "C" __global__ __launch_bounds__(256) void sdc_rhs4_node0(TransArgs a) { rhs4_body<KIND_NODE0>(a); }
+extern "C" __global__ __launch_bounds__(256) void sdc_rhs4_later(TransArgs a) { rhs4_body<KIND_LATER>(a); }
+
+// Newton inputs at zone centres: rho_c and b_c = (rhs_c X, rhs_c E - KE_c)
+extern "C" __global__ __launch_bounds__(256) void sdc_newton_inputs4(O4Args a) {
+  const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= a.Z) return;
+  const i64 Z = a.Z;
+  int c[3];
+  zone_coords(z, a.n, c);
+  double rc[SDC_NC];
+  for (int q = 0; q < SDC_NC; ++q) {
+    const double* u = a.U + (i64)q * Z;
+    const double u0 = u[z];
+    rc[q] = u0 - lap_sum(u, c, a.n, u0) / 24.0;
+  }
+  double ke = 0.0;
+#pragma unroll
+  for (int d = 0; d < SDC_DIM; ++d) ke = fma(rc[1 + d], rc[1 + d], ke);
+  ke = 0.5 * ke / rc[0];
+  a.rho_c[z] = rc[0];
+#pragma unroll
+  for (int s = 0; s < SDC_NS; ++s) a.b_c[(i64)s * Z + z] = rc[SDC_NH + s];
+  a.b_c[(i64)(SDC_NX - 1) * Z + z] = rc[1 + SDC_DIM] - ke;
+}
+
+// <R> = R_c + lap(R_c) / 24; U^{m+1} = rhs + dt_m <R> (reacting components;
+// rho and rho u are the rhs); R^{m+1} = <R>
+extern "C" __global__ __launch_bounds__(256) void sdc_average_store4(O4Args a) {
+  const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= a.Z) return;
+  const i64 Z = a.Z;
+  int c[3];
+  zone_coords(z, a.n, c);
+  for (int i = 0; i < SDC_NX; ++i) {
+    const double* r = a.R_c + (i64)i * Z;
+    const double r0 = r[z];
+    const double ravg = r0 + lap_sum(r, c, a.n, r0) / 24.0;
+    a.R[(i64)i * Z + z] = ravg;
+    const int q = i == SDC_NX - 1 ? 1 + SDC_DIM : SDC_NH + i;
+    a.U[(i64)q * Z + z] = fma(a.dtm, ravg, a.U[(i64)q * Z + z]);
+  }
+}
+
 extern "C" __global__ void sdc_reset_counter(unsigned* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0u;
 }

@@ -106,14 +106,57 @@ std::vector<double> lobatto_nodes(int n) {
   return {};
 }
 
+// Right Radau points for 1..4 points on (0, 1], preceded by tau_0 = 0 (the
+// start of the step, not a quadrature point): the zeros of
+// P_s(x) - P_{s-1}(x) on [-1, 1] mapped to t = (x + 1) / 2, the largest of
+// which is x = 1.  The s - 1 interior zeros are bracketed on a fine grid and
+// bisected to the last bit.
+std::vector<double> radau_nodes(int n) {
+  const int s = n - 1;
+  auto q = [s](double x) {  // P_s(x) - P_{s-1}(x) by the three-term recurrence
+    double p0 = 1.0, p1 = x;
+    if (s == 1) return p1 - p0;
+    for (int k = 2; k <= s; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    return p1 - p0;
+  };
+  std::vector<double> tau{0.0};
+  const int grid = 4096;
+  for (int i = 0; i < grid; ++i) {
+    double lo = -1.0 + 1.9 * i / grid, hi = -1.0 + 1.9 * (i + 1) / grid;
+    double flo = q(lo);
+    if ((flo < 0.0) == (q(hi) < 0.0)) continue;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      const double fm = q(mid);
+      if ((fm < 0.0) == (flo < 0.0)) {
+        lo = mid;
+        flo = fm;
+      } else {
+        hi = mid;
+      }
+    }
+    tau.push_back(0.5 * (0.5 * (lo + hi) + 1.0));
+  }
+  tau.push_back(1.0);
+  return tau;
+}
+
 // S[m][j] = integral over [tau_m, tau_{m+1}] of the Lagrange polynomial l_j
-// through all nodes: the node-to-node quadrature of the integral in Eq. 2.
-std::vector<std::vector<double>> integration_matrix(const std::vector<double>& tau) {
+// through the interpolation points tau[first..]: the node-to-node quadrature
+// of the integral in Eq. 2 (columns j < first are zero).  Gauss-Lobatto nodes
+// interpolate through every node (first = 0), right Radau nodes through the
+// Radau points only (first = 1).
+std::vector<std::vector<double>> integration_matrix(const std::vector<double>& tau, int first) {
   const int n = (int)tau.size();
   std::vector<std::vector<double>> S(n - 1, std::vector<double>(n, 0.0));
-  for (int j = 0; j < n; ++j) {
+  for (int j = first; j < n; ++j) {
     std::vector<double> c(1, 1.0);  // power-series coefficients of l_j
-    for (int i = 0; i < n; ++i) {
+    for (int i = first; i < n; ++i) {
       if (i == j) continue;
       const double den = tau[j] - tau[i];
       std::vector<double> nc(c.size() + 1, 0.0);
@@ -329,6 +372,18 @@ int prepare(const sdc_config* cfg, const sdc_network* net, Prepared* P, std::str
     *err = "n_nodes must be in 2..5";
     return SDC_ERR_UNSUPPORTED;
   }
+  if (c.node_type != SDC_NODES_LOBATTO && c.node_type != SDC_NODES_RADAU) {
+    *err = "node_type must be SDC_NODES_LOBATTO or SDC_NODES_RADAU";
+    return SDC_ERR_ARG;
+  }
+  if (c.space_order != 2 && c.space_order != 4) {
+    *err = "space_order must be 2 or 4";
+    return SDC_ERR_ARG;
+  }
+  if (c.space_order == 4 && c.nbox > 0) {
+    *err = "the fourth-order method supports single grids only";
+    return SDC_ERR_UNSUPPORTED;
+  }
   if (c.n_iters < 1) {
     *err = "n_iters must be >= 1";
     return SDC_ERR_ARG;
@@ -434,6 +489,14 @@ struct sdc_handle_s {
   std::vector<double*> adj_buf;
   hipFunction_t f_first_o2 = nullptr, f_node0_o2 = nullptr, f_later_o2 = nullptr, f_trans_finish = nullptr,
                 f_solve_o2 = nullptr, f_solve_finish = nullptr, f_reset = nullptr;
+  // fourth order in space: kernels and workspace (allocated on first use):
+  // face fluxes F [NC][Z], zone-centre density [Z], Newton rhs, iterate and
+  // source [NX][Z] each, iteration counts [Z]
+  hipFunction_t f_flux4[3] = {nullptr, nullptr, nullptr}, f_div4[3] = {nullptr, nullptr, nullptr},
+                f_conv4 = nullptr, f_source4c = nullptr, f_rhs4[3] = {nullptr, nullptr, nullptr},
+                f_newin4 = nullptr, f_avgst4 = nullptr;
+  double *o4_F = nullptr, *o4_rho = nullptr, *o4_b = nullptr, *o4_x = nullptr, *o4_R = nullptr;
+  int* o4_it = nullptr;
   // deferred-zone queue (capacity Z, allocated on first use) and the tuned
   // kernel choice: occupancy-2 variants and the fast-pass iteration cap
   DeferQueue q{};
@@ -501,6 +564,13 @@ int fail(sdc_handle h, int code, const std::string& msg) {
 
 int kind_of(const sdc_handle h, hipFunction_t f) {
   if (f == h->f_advect || f == h->f_advect_rows) return SDC_K_ADVECT;
+  for (int d = 0; d < 3; ++d)
+    if (f && (f == h->f_flux4[d] || f == h->f_div4[d])) return SDC_K_ADVECT;
+  if (f && (f == h->f_source4c || f == h->f_conv4)) return SDC_K_SOURCE;
+  if (f && f == h->f_rhs4[0]) return SDC_K_TRANSITION_FIRST;
+  if (f && f == h->f_rhs4[1]) return SDC_K_TRANSITION_NODE0;
+  if (f && f == h->f_rhs4[2]) return SDC_K_TRANSITION_LATER;
+  if (f && (f == h->f_newin4 || f == h->f_avgst4)) return SDC_K_ORDER4;
   if (f == h->f_source) return SDC_K_SOURCE;
   if (f == h->f_solve) return SDC_K_SOLVE;
   if (f == h->f_solve_o2) return SDC_K_SOLVE;
@@ -616,6 +686,30 @@ void free_queue(sdc_handle h) {
   h->q_ready = false;
 }
 
+int ensure_o4(sdc_handle h) {
+  if (h->o4_F) return SDC_OK;
+  const size_t Z = (size_t)h->P.Z;
+  if (hipMalloc((void**)&h->o4_F, h->nc * Z * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&h->o4_rho, Z * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&h->o4_b, h->nx * Z * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&h->o4_x, h->nx * Z * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&h->o4_R, h->nx * Z * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&h->o4_it, Z * sizeof(int)) != hipSuccess)
+    return fail(h, SDC_ERR_NOMEM, "hipMalloc(fourth-order workspace) failed");
+  return SDC_OK;
+}
+
+void free_o4(sdc_handle h) {
+  for (void* p : {(void*)h->o4_F, (void*)h->o4_rho, (void*)h->o4_b, (void*)h->o4_x, (void*)h->o4_R, (void*)h->o4_it})
+    if (p) (void)hipFree(p);
+  h->o4_F = h->o4_rho = h->o4_b = h->o4_x = h->o4_R = nullptr;
+  h->o4_it = nullptr;
+}
+
+void grid_extents(const sdc_handle h, int* n) {
+  for (int d = 0; d < 3; ++d) n[d] = d < h->P.cfg.dim ? (int)h->P.cfg.n[d] : 1;
+}
+
 int reset_queue(sdc_handle h, hipStream_t s) {
   void* params[] = {&h->q.count};
   HIP_CHECK(h, hipModuleLaunchKernel(h->f_reset, 1, 1, 1, 64, 1, 1, 0, s, params, nullptr));
@@ -699,9 +793,32 @@ int upload_rows(sdc_handle h) {
   return SDC_OK;
 }
 
+// Fourth-order A: per direction the face-averaged fluxes, then their
+// difference into A.
+int advect4(sdc_handle h, const double* U, double* A, hipStream_t s) {
+  if (int rc = ensure_o4(h)) return rc;
+  const sdc_config& c = h->P.cfg;
+  Flux4Args a;
+  std::memset(&a, 0, sizeof a);
+  a.U = U;
+  a.F = h->o4_F;
+  a.A = A;
+  a.Z = h->P.Z;
+  grid_extents(h, a.n);
+  a.gamma = c.gamma;
+  for (int d = 0; d < c.dim; ++d) {
+    a.first = d == 0;
+    a.idx = 1.0 / c.dx[d];
+    if (int rc = launch(h, h->f_flux4[d], h->P.Z, &a, s)) return rc;
+    if (int rc = launch(h, h->f_div4[d], h->P.Z, &a, s)) return rc;
+  }
+  return SDC_OK;
+}
+
 int advect(sdc_handle h, const double* U, double* A, hipStream_t s) {
   const sdc_config& c = h->P.cfg;
   if (!c.advection) return fill(h, A, (int64_t)h->nc * h->P.Z, 0.0, s);
+  if (c.space_order == 4) return advect4(h, U, A, s);
   AdvArgs a;
   std::memset(&a, 0, sizeof a);
   a.U = U;
@@ -727,7 +844,31 @@ int advect(sdc_handle h, const double* U, double* A, hipStream_t s) {
   return launch(h, h->f_advect, h->P.Z, &a, s);
 }
 
+// Fourth-order <R(U)>: R at the zone-centre values, converted to averages.
+int source4(sdc_handle h, const double* U, double* R, hipStream_t s) {
+  if (int rc = ensure_o4(h)) return rc;
+  O4Args o;
+  std::memset(&o, 0, sizeof o);
+  o.Z = h->P.Z;
+  grid_extents(h, o.n);
+  o.U = (double*)U;
+  o.R = h->o4_R;
+  o.P = h->d_params;
+  o.gm1 = h->P.cfg.gamma - 1.0;
+  if (int rc = launch(h, h->f_source4c, h->P.Z, &o, s)) return rc;
+  ConvArgs cv;
+  std::memset(&cv, 0, sizeof cv);
+  cv.src = h->o4_R;
+  cv.dst = R;
+  cv.Z = h->P.Z;
+  grid_extents(h, cv.n);
+  cv.ncomp = h->nx;
+  cv.sign = 1.0;
+  return launch(h, h->f_conv4, h->P.Z, &cv, s);
+}
+
 int source(sdc_handle h, const double* U, double* R, hipStream_t s) {
+  if (h->P.cfg.space_order == 4) return source4(h, U, R, s);
   SourceArgs a{h->P.Z, U, R, h->d_params, h->P.cfg.gamma - 1.0};
   return launch(h, h->f_source, h->P.Z, &a, s);
 }
@@ -786,6 +927,45 @@ int split_transition(sdc_handle h, int kind, TransArgs a, hipStream_t s) {
   return SDC_OK;
 }
 
+// Fourth-order transition m -> m+1: the rhs of Eq. 2 (zone averages) into
+// the node's output array and the Newton guess into the workspace, the
+// zone-centre Newton inputs, the per-zone solve (the sdc_reaction_solve
+// kernels), then <R> = R_c + lap R_c / 24 and U^{m+1} = rhs + dt_m <R>.
+int transition4(sdc_handle h, int kind, TransArgs a, hipStream_t s) {
+  if (int rc = ensure_o4(h)) return rc;
+  a.x4 = h->o4_x;
+  if (int rc = launch(h, h->f_rhs4[kind], h->P.Z, &a, s)) return rc;
+  O4Args o;
+  std::memset(&o, 0, sizeof o);
+  o.Z = h->P.Z;
+  grid_extents(h, o.n);
+  o.dtm = a.dtm;
+  o.U = a.Uout;
+  o.R = a.Rout;
+  o.rho_c = h->o4_rho;
+  o.b_c = h->o4_b;
+  o.R_c = h->o4_R;
+  if (int rc = launch(h, h->f_newin4, h->P.Z, &o, s)) return rc;
+  SolveArgs v;
+  std::memset(&v, 0, sizeof v);
+  v.Z = h->P.Z;
+  v.dtm = a.dtm;
+  v.rho = h->o4_rho;
+  v.b = h->o4_b;
+  v.x = h->o4_x;
+  v.R = h->o4_R;
+  v.iters = h->o4_it;
+  v.P = h->d_params;
+  v.gm1 = h->P.cfg.gamma - 1.0;
+  v.ctl = newton_ctl(h);
+  v.stats = h->d_stats;
+  v.q = h->q;
+  if (int rc = reset_queue(h, s)) return rc;
+  if (int rc = launch(h, h->occ2 ? h->f_solve_o2 : h->f_solve, h->P.Z, &v, s)) return rc;
+  if (int rc = launch(h, h->f_solve_finish, std::min<int64_t>(h->P.Z, kFinishThreads), &v, s)) return rc;
+  return launch(h, h->f_avgst4, h->P.Z, &o, s);
+}
+
 // One iteration k -> k+1 over the M transitions, then A at node M.
 int sweep(sdc_handle h, double dt, int k, const sdc_nodes& n, hipStream_t s) {
   const int M = h->M;
@@ -820,9 +1000,12 @@ int sweep(sdc_handle h, double dt, int k, const sdc_nodes& n, hipStream_t s) {
     a.stats = h->d_stats;
     a.q = h->q;
     const int kind = k == 0 ? 0 : (m == 0 ? 1 : 2);
-    int rc = reset_queue(h, s);
-    if (rc) return rc;
-    if (h->split > 0 && !h->capturing) {
+    int rc;
+    if (h->P.cfg.space_order == 4) {
+      if ((rc = transition4(h, kind, a, s))) return rc;
+    } else if ((rc = reset_queue(h, s))) {
+      return rc;
+    } else if (h->split > 0 && !h->capturing) {
       if ((rc = split_transition(h, kind, a, s))) return rc;
     } else {
       hipFunction_t f = kind == 0 ? (h->occ2 ? h->f_first_o2 : h->f_first)
@@ -1219,6 +1402,8 @@ int sdc_config_default(sdc_config* cfg) {
   cfg->box_n = nullptr;
   cfg->graph = 0;
   cfg->autotune = 0;
+  cfg->node_type = SDC_NODES_LOBATTO;
+  cfg->space_order = 2;
   return SDC_OK;
 }
 
@@ -1284,8 +1469,9 @@ int sdc_init(const sdc_config* cfg, const sdc_network* net, sdc_handle* out) {
   h->nx = h->ns + 1;
   h->M = h->P.cfg.n_nodes - 1;
   h->nra = h->P.topo.nr > 0 ? h->P.topo.nr : 1;
-  h->tau = lobatto_nodes(h->P.cfg.n_nodes);
-  h->S = integration_matrix(h->tau);
+  const bool radau = h->P.cfg.node_type == SDC_NODES_RADAU;
+  h->tau = radau ? radau_nodes(h->P.cfg.n_nodes) : lobatto_nodes(h->P.cfg.n_nodes);
+  h->S = integration_matrix(h->tau, radau ? 1 : 0);
   std::vector<char> code;
   rc = get_code_object(h->P.source, &code, &err);
   if (rc) {
@@ -1326,7 +1512,27 @@ int sdc_init(const sdc_config* cfg, const sdc_network* net, sdc_handle* out) {
   // row is longer than 256 zones (SDC_ADVECT_ROWS=0: the zone-per-thread
   // kernel everywhere)
   const char* ev = std::getenv("SDC_ADVECT_ROWS");
-  if (h->P.cfg.advection && rows_kernel_fits(h->P) && !(ev && ev[0] == '0')) {
+  {
+    // fourth-order kernels (the flux and divergence kernels exist per direction)
+    const char* f4[] = {"sdc_flux4_0", "sdc_flux4_1", "sdc_flux4_2"};
+    const char* d4[] = {"sdc_div4_0", "sdc_div4_1", "sdc_div4_2"};
+    for (int d = 0; d < h->P.cfg.dim; ++d) {
+      if (hipModuleGetFunction(&h->f_flux4[d], h->mod, f4[d]) != hipSuccess ||
+          hipModuleGetFunction(&h->f_div4[d], h->mod, d4[d]) != hipSuccess)
+        return bail(SDC_ERR_HIP, std::string("missing kernel ") + f4[d]);
+    }
+    struct {
+      hipFunction_t* f;
+      const char* name;
+    } f4s[] = {{&h->f_conv4, "sdc_convert4"},     {&h->f_source4c, "sdc_source4_centre"},
+               {&h->f_rhs4[0], "sdc_rhs4_first"}, {&h->f_rhs4[1], "sdc_rhs4_node0"},
+               {&h->f_rhs4[2], "sdc_rhs4_later"}, {&h->f_newin4, "sdc_newton_inputs4"},
+               {&h->f_avgst4, "sdc_average_store4"}};
+    for (auto& fn : f4s)
+      if (hipModuleGetFunction(fn.f, h->mod, fn.name) != hipSuccess)
+        return bail(SDC_ERR_HIP, std::string("missing kernel ") + fn.name);
+  }
+  if (h->P.cfg.advection && h->P.cfg.space_order == 2 && rows_kernel_fits(h->P) && !(ev && ev[0] == '0')) {
     h->row_bw = longest_row(h->P) > kBlock ? 512 : kBlock;
     const bool wide = h->row_bw > kBlock;
     const char* name = h->P.cfg.slope == 0 ? (wide ? "sdc_advect_rows_wc" : "sdc_advect_rows_c")
@@ -1382,6 +1588,7 @@ int sdc_destroy(sdc_handle h) {
   for (double* p : h->adj_buf) (void)hipFree(p);
   free_queue(h);
   free_split(h);
+  free_o4(h);
   if (h->d_params) (void)hipFree(h->d_params);
   if (h->d_box_off) (void)hipFree(h->d_box_off);
   if (h->d_box_ext) (void)hipFree(h->d_box_ext);
@@ -1571,6 +1778,7 @@ int sdc_step_adjoint(sdc_handle h, double dt, const double* U_n, const double* U
     return fail(h, SDC_ERR_ARG, "Ubar_n must not alias U_n or Ubar_np1");
   const sdc_config& c = h->P.cfg;
   if (c.nbox > 0) return fail(h, SDC_ERR_UNSUPPORTED, "the adjoint supports single grids only");
+  if (c.space_order != 2) return fail(h, SDC_ERR_UNSUPPORTED, "the adjoint supports the second-order method only");
   if (c.advection && !(c.slope == 0 && c.alpha > 0.0))
     return fail(h, SDC_ERR_UNSUPPORTED, "the adjoint needs the smooth mode: slope 0 and a frozen alpha > 0");
   if (c.n_iters > 8) return fail(h, SDC_ERR_UNSUPPORTED, "the adjoint supports up to 8 SDC iterations");

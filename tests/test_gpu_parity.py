@@ -23,7 +23,7 @@ def make(name, shape=None, **over):
     from paper_1910_12578_amd import SDC, config_from_workload
     w = si.workload(name, shape=shape or SHAPES[name])
     prob_over = {k: v for k, v in over.items() if k in ("n_nodes", "n_iters", "slope", "alpha", "advection",
-                                                         "newton_maxiter", "newton_tol")}
+                                                         "newton_maxiter", "newton_tol", "node_type")}
     prob = osdc.Problem.from_workload(w, **prob_over)
     cfg = config_from_workload(w, **over)
     return w, prob, SDC(cfg, w["network"])
@@ -132,6 +132,13 @@ def test_sweep_iterations_match():
     ("net2d", 1, {"n_nodes": 4, "n_iters": 3}),
     ("net2d", 1, {"n_nodes": 5, "n_iters": 2}),
     ("net2d", 1, {"advection": 0}),
+    # right Radau node sets (1..4 Radau points after tau_0 = 0)
+    ("net2d", 1, {"node_type": "radau", "n_nodes": 2, "n_iters": 2}),
+    ("net2d", 2, {"node_type": "radau", "n_nodes": 3, "n_iters": 4}),
+    ("net2d", 1, {"node_type": "radau", "n_nodes": 4, "n_iters": 3}),
+    ("net2d", 1, {"node_type": "radau", "n_nodes": 5, "n_iters": 2}),
+    ("net3d", 1, {"node_type": "radau", "n_nodes": 3, "n_iters": 4}),
+    ("chain1d", 10, {"node_type": "radau"}),
 ])
 def test_step_matches_oracle(name, nsteps, over):
     w, prob, h = make(name, **over)
