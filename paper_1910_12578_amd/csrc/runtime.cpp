@@ -1254,8 +1254,8 @@ int step_adjoint(sdc_handle h, double dt, const double* Un, const double* Ubar1,
 std::string tune_path(const sdc_handle h) {
   const sdc_config& c = h->P.cfg;
   char name[128];
-  std::snprintf(name, sizeof name, "tune4_%016llx_z%lld_k%d_a%d.txt", (unsigned long long)fnv1a(h->P.source),
-                (long long)h->P.Z, (int)c.n_iters, (int)c.advection);
+  std::snprintf(name, sizeof name, "tune4_%016llx_z%lld_k%d_a%d_s%d_n%d.txt", (unsigned long long)fnv1a(h->P.source),
+                (long long)h->P.Z, (int)c.n_iters, (int)c.advection, (int)c.space_order, (int)c.node_type);
   return cache_dir() + "/" + name;
 }
 

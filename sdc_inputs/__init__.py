@@ -213,9 +213,9 @@ def box_state(extents, nspec, seed=SEEDS["boxes_state"] + 1, sigma=0.3, vel=0.05
               gamma=GAMMA):
     """Concatenated SoA state of independent periodic boxes.
 
-    Per zone T = exp(sigma zeta), zeta ~ N(0,1) truncated to [-3, 3] (beyond
-    3 sigma, T > 2.46, zones run away thermally within one step and the stiff
-    SDC iteration diverges); isobaric rho = 1/T; velocity
+    Per zone T = exp(sigma zeta), zeta ~ N(0,1) (the lognormal of the batched
+    workload, untruncated: the draw of the standard seed spans |zeta| <= 5.95,
+    T from 0.17 to 5.96); isobaric rho = 1/T; velocity
     0.05 sin of box-local coordinates; X as in `reactive_state`.  Returns
     (U [n_c, Ztot], offsets [nbox+1]).
     """
@@ -224,12 +224,8 @@ def box_state(extents, nspec, seed=SEEDS["boxes_state"] + 1, sigma=0.3, vel=0.05
     nzones = np.prod(extents, axis=1)
     offsets = np.concatenate([[0], np.cumsum(nzones)]).astype(np.int64)
     ztot = int(offsets[-1])
-    # lognormal temperature, the normal truncated at +-3 (redrawn outside)
+    # lognormal temperature
     zeta = g.standard_normal(ztot)
-    out = np.abs(zeta) > 3.0
-    while out.any():
-        zeta[out] = g.standard_normal(int(out.sum()))
-        out = np.abs(zeta) > 3.0
     T = np.exp(sigma * zeta)
     rho = 1.0 / T
     p = np.ones(ztot)
@@ -301,10 +297,12 @@ def boxes_workload(nbox=4096, choices=(8, 16, 32, 64), sigma=0.3, seed=SEEDS["bo
     iid uniform over `choices`, the 13-species network, per-zone lognormal
     temperature (so Newton iteration counts spread), dx = 1/256 in every box.
 
-    The step is `dt_factor` times the CFL step: with the lognormal spread
-    (T up to 2.46) the full CFL step puts the hottest zones in thermal
-    runaway, where the SDC iteration of the stiff source diverges; a
-    burning-limited step of 0.2 CFL keeps the zones convergent.
+    The step is `dt_factor` times the CFL step (a burning-limited step) and
+    the nodes are tau_0 = 0 plus two right Radau points (K = 4): in the hot
+    tail of the lognormal (T up to 6) the Gauss-Lobatto sweeps, whose fixed
+    point does not damp stiff modes, drive mass fractions negative and some
+    Newton solves stop converging, and the advective term then carries the
+    failure to neighbouring zones; the Radau sweeps converge in every zone.
 
     U0 is the concatenated SoA state [n_c, sum of box zones]; box_off holds the
     zone offsets of the boxes.
@@ -315,4 +313,4 @@ def boxes_workload(nbox=4096, choices=(8, 16, 32, 64), sigma=0.3, seed=SEEDS["bo
     dx = [1.0 / 256] * 3
     return dict(name="boxes", dim=3, shape=None, box_n=ext, box_off=offsets, dx=dx, gamma=GAMMA,
                 network=net, U0=U0, dt=dt_factor * cfl_dt(rho, u, p, dx, cfl=0.5), alpha=-1.0, n_nodes=3,
-                n_iters=4, steps=10, slope=1, cfl=0.5, newton_tol=1e-13, newton_maxiter=50)
+                node_type="radau", n_iters=4, steps=10, slope=1, cfl=0.5, newton_tol=1e-13, newton_maxiter=50)

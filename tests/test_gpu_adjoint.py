@@ -103,6 +103,25 @@ def test_parameter_gradient_matches_oracle_complex_step():
     assert np.all(err <= 1e-8), (g, ref)
 
 
+def test_parameter_gradient_64sq_20_steps_matches_oracle():
+    """The adjoint at 64^2 zones over 20 steps against the oracle's
+    complex-step gradient of the same run (stored by
+    tests/golden/make_adjoint_gradient.py, which calls only the oracle)."""
+    from paper_1910_12578_amd.autograd import theta_of
+    from tests import golden
+    ref = golden.read("adjoint_gradient_64sq_20steps.txt")
+    ref = np.concatenate([ref["dlnA"], ref["dE"]])
+    w, h, q = setup(shape=(64, 64))
+    nc = w["U0"].shape[0]
+    theta = theta_of(w["network"]).requires_grad_(True)
+    J = objective(h, w, q, to_gpu(w["U0"].reshape(nc, -1)), theta, 20)
+    J.backward()
+    g = theta.grad.numpy()
+    err = np.abs(g - ref) / np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
+    print("adjoint 64^2 x 20 vs oracle complex step: max scaled error", err.max())
+    assert np.all(err <= 1e-8), (g, ref)
+
+
 def test_state_gradient_directional_derivative():
     import torch
     from paper_1910_12578_amd.autograd import theta_of

@@ -47,11 +47,13 @@ def core_zones(idx, W, shape):
     return lin.ravel(), sl
 
 
-def gpu_step(w, precision, nsteps=1):
+def gpu_step(w, precision, nsteps=1, schedule=None):
     import torch
     from paper_1910_12578_amd import SDC, config_from_workload
     nc = w["U0"].shape[0]
     with SDC(config_from_workload(w, precision=precision), w["network"]) as h:
+        if schedule is not None:
+            h.set_schedule(*schedule)
         U = torch.from_numpy(w["U0"].reshape(nc, -1)).to("cuda")
         h.step(w["dt"], nsteps, U)
         torch.cuda.synchronize()
@@ -84,13 +86,17 @@ def net3d_full():
     return w, refs
 
 
-@pytest.mark.parametrize("precision,tol", [(0, TOL_FP64), (1, TOL_MIXED)])
-def test_net3d_256cubed_sampled_windows(net3d_full, precision, tol):
-    """256^3 x 13 species, one step as bench.py runs it, against the oracle on
-    two 37^3 windows (core 5^3 each), and global conservation."""
+# the schedules the autotuner picks at 256^3 (two-wave FP64 transitions, the
+# compiler's budget in mixed precision, 128-plane advection tiles, which cut
+# the z extent into two chunks) and the default one
+@pytest.mark.parametrize("precision,tol,schedule", [(0, TOL_FP64, (1, 0, 0, 128)), (1, TOL_MIXED, (0, 0, 0, 128)),
+                                                    (0, TOL_FP64, (0, 0, 0, 0))])
+def test_net3d_256cubed_sampled_windows(net3d_full, precision, tol, schedule):
+    """256^3 x 13 species, one step in the schedule bench.py times, against
+    the oracle on two 37^3 windows (core 5^3 each), and global conservation."""
     import torch
     w, refs = net3d_full
-    U, st = gpu_step(w, precision)
+    U, st = gpu_step(w, precision, schedule=schedule)
     assert st["failed"] == 0 and st["nonfinite"] == 0
     for lin, ref in refs:
         got = U[:, torch.from_numpy(lin).to("cuda")].cpu().numpy()

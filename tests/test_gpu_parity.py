@@ -88,7 +88,12 @@ def test_reaction_solve(name, precision):
     xg, Rg, nug = h.reaction_solve(dtm, to_gpu(rho), to_gpu(b), to_gpu(x0))
     tol = TOL_FP64 if precision == 0 else TOL_MIXED
     assert_close(to_np(xg), x, tol, f"x {name} p{precision}")
-    assert_close(to_np(Rg), R, 100 * tol, f"R(x) {name} p{precision}")
+    # R at the root: the roots agree to the Newton tolerance, and R amplifies
+    # that difference by |dR/dx| |x| / |R|, large for the stiff rates; so R is
+    # checked as a function at the GPU's own root (FP64 in both modes), at
+    # the FP64 bar
+    R_at_root = osdc.R_of_x(to_np(xg), rho, prob)
+    assert_close(to_np(Rg), R_at_root, TOL_FP64, f"R(x) {name} p{precision}")
     nug = to_np(nug)
     assert np.all(nug > 0) and np.all(nu > 0)
     if precision == 0:

@@ -40,6 +40,24 @@ def test_step_schedules_bitwise_identical(name, precision):
         assert s == sref, sched
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_row_tiles_spanning_several_chunks_bitwise_identical(precision):
+    """A z extent of 300 planes: 128-plane tiles (the one the tuner picks at
+    256^3) cut it into chunks of 128, 128 and 44, 64-plane tiles into five;
+    every tile and the bench's schedules give the default bits."""
+    w, prob, h = make("net3d", shape=(8, 3, 300), precision=precision)
+    ref, sref = one_step(h, w, 1)
+    for sched in [(1, 0, 0, 128), (0, 0, 0, 128), (0, 0, 0, 64), (1, 6, 0, 128)]:
+        h.set_schedule(*sched)
+        U, s = one_step(h, w, 1)
+        assert bool((U == ref).all()), sched
+        assert s == sref, sched
+    h.set_schedule(0, 0, 0, 0)
+    nc = w["U0"].shape[0]
+    e = rel_err_per_component(to_np(ref), osdc.run(w["U0"], w["dt"], 1, prob).reshape(nc, -1))
+    assert np.all(e <= TOL_FP64 if precision == 0 else 1e-8), e
+
+
 @pytest.mark.parametrize("cap", [1, 2, 5])
 def test_reaction_solve_schedules_bitwise_identical(cap):
     w, prob, h = make("net2d")
