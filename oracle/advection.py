@@ -45,22 +45,29 @@ def advective_term(U, dim, dx, gamma, slope=1, alpha=-1.0):
     A = np.zeros_like(U)
     for d in range(dim):
         ax = U.ndim - 1 - d
-        Um = np.roll(U, 1, axis=ax)
-        Up = np.roll(U, -1, axis=ax)
-        if slope == 0:
-            dU = 0.5 * (Up - Um)
-        else:
-            dU = mc_slope(U - Um, Up - U)
-        UL = U + 0.5 * dU                       # left state at face i+1/2
-        UR = np.roll(U - 0.5 * dU, -1, axis=ax)  # right state at face i+1/2
-        FL, uL, pL = euler_flux(UL, d, dim, gamma)
-        FR, uR, pR = euler_flux(UR, d, dim, gamma)
-        if alpha > 0:
-            a = alpha
-        else:
-            cL = eos.sound_speed(UL[0], pL, gamma)
-            cR = eos.sound_speed(UR[0], pR, gamma)
-            a = np.maximum(np.abs(uL) + cL, np.abs(uR) + cR)[None]
-        Fh = 0.5 * (FL + FR) - 0.5 * a * (UR - UL)  # flux through face i+1/2
+        Fh = face_flux(U, d, dim, gamma, slope, alpha)
         A -= (Fh - np.roll(Fh, 1, axis=ax)) / dx[d]
     return A
+
+
+def face_flux(U, d, dim, gamma, slope=1, alpha=-1.0):
+    """Rusanov flux through the face i+1/2 along direction d of every zone
+    (periodic grid)."""
+    ax = U.ndim - 1 - d
+    Um = np.roll(U, 1, axis=ax)
+    Up = np.roll(U, -1, axis=ax)
+    if slope == 0:
+        dU = 0.5 * (Up - Um)
+    else:
+        dU = mc_slope(U - Um, Up - U)
+    UL = U + 0.5 * dU                       # left state at face i+1/2
+    UR = np.roll(U - 0.5 * dU, -1, axis=ax)  # right state at face i+1/2
+    FL, uL, pL = euler_flux(UL, d, dim, gamma)
+    FR, uR, pR = euler_flux(UR, d, dim, gamma)
+    if alpha > 0:
+        a = alpha
+    else:
+        cL = eos.sound_speed(UL[0], pL, gamma)
+        cR = eos.sound_speed(UR[0], pR, gamma)
+        a = np.maximum(np.abs(uL) + cL, np.abs(uR) + cR)[None]
+    return 0.5 * (FL + FR) - 0.5 * a * (UR - UL)

@@ -214,20 +214,20 @@ def node_times(prob: Problem):
     return quadrature.node_set(prob.node_type, prob.n_nodes)
 
 
-def sweep(Un, A, R, U, dt, prob: Problem, stats: Stats | None = None):
+def sweep(Un, A, R, U, dt, prob: Problem, stats: Stats | None = None, level=None):
     """One SDC iteration k -> k+1 over all node transitions (Eq. 2).
 
     Un: U^n.  A, R, U: lists over nodes of iteration-k values (A[0], R[0] are
     A(U^n), R(U^n)).  Returns the iteration-(k+1) lists (U_new, A_new, R_new).
+    `level` (refined patches, see amr.py) supplies prepare(U, node), applied
+    to each new node state before its advective term (ghost zones), and A(U).
     """
     tau, S = node_times(prob)
     M = prob.n_nodes - 1
     U_new, A_new, R_new = [Un], [A[0]], [R[0]]
     for m in range(M):
         dtm = (tau[m + 1] - tau[m]) * dt
-        Am = A_new[m] if m == 0 else A_of(U_new[m], prob)
-        if m > 0:
-            A_new.append(Am)
+        Am = A_new[m]
         integral = dt * sum(S[m, j] * (A[j] + R[j]) for j in range(M + 1))
         rhs = U_new[m] + dtm * (Am - A[m]) - dtm * R[m + 1] + integral
         _, _, x0, _ = split_state(U[m + 1], prob)
@@ -246,7 +246,11 @@ def sweep(Un, A, R, U, dt, prob: Problem, stats: Stats | None = None):
             R_new.append(R_full_from_x(R_of_x(x, rho, prob), prob))
         if stats is not None:
             stats.add(nu)
-    A_new.append(A_of(U_new[M], prob))
+        if level is not None:
+            U_new[m + 1] = level.prepare(U_new[m + 1], m + 1)
+            A_new.append(level.A(U_new[m + 1]))
+        else:
+            A_new.append(A_of(U_new[m + 1], prob))
     return U_new, A_new, R_new
 
 
