@@ -349,6 +349,40 @@ def run_boxes(w, steps, warmup, precision, schedule="auto", graphs=(0, 1)):
     return out
 
 
+def run_amr(w, patches, steps, warmup):
+    """Two-level hierarchy: the single-grid workload as the coarse level and
+    `patches` (lo, ext in coarse zones) refined by 2 with subcycling.  The
+    timed coarse steps start from the initial state with interpolated patches;
+    zone-updates count every coarse zone once and every patch zone (ghosts
+    excluded) twice per coarse step."""
+    import torch
+    from paper_1910_12578_amd import AMR, config_from_workload
+    a = AMR(config_from_workload(w, autotune=1), w["network"], patches)
+    nc = w["U0"].shape[0]
+    U0 = torch.from_numpy(w["U0"].reshape(nc, -1)).to("cuda")
+    Uc = U0.clone()
+    Uf = torch.empty((nc, a.zf), dtype=torch.float64, device="cuda")
+    a.fill_patches(Uc, Uf)
+    if warmup:
+        a.step(w["dt"], warmup, Uc, Uf)
+    Uc.copy_(U0)
+    a.fill_patches(Uc, Uf)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a.step(w["dt"], steps, Uc, Uf)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    fine = sum(int(np.prod([2 * e for e in ext])) for _, ext in patches)
+    updates = (w["U0"][0].size + 2 * fine) * steps
+    st = a.stats()
+    a.close()
+    del U0, Uc, Uf
+    torch.cuda.empty_cache()
+    return dict(zone_updates=updates / el, ms_per_step=1e3 * el / steps, coarse_zones=w["U0"][0].size,
+                patch_zones=fine, patches=[dict(lo=list(lo), ext=list(ext)) for lo, ext in patches],
+                failed=st[0]["failed"] + st[1]["failed"], nonfinite=st[0]["nonfinite"] + st[1]["nonfinite"])
+
+
 def _oracle_block(args):
     """One oracle step on one sub-block (runs in a worker process)."""
     light, U0, dt = args
@@ -453,6 +487,7 @@ def main():
     ap.add_argument("--no-boxes", action="store_true", help="skip the batched-box workload")
     ap.add_argument("--no-net2d", action="store_true", help="skip the 2D 512^2 workload")
     ap.add_argument("--no-order4", action="store_true", help="skip the fourth-order-in-space leg")
+    ap.add_argument("--no-amr", action="store_true", help="skip the refined-patch (two-level) leg")
     ap.add_argument("--space-order", type=int, default=2, choices=(2, 4), help="spatial order of the main workload")
     ap.add_argument("--node-type", default="lobatto", choices=("lobatto", "radau"), help="nodes of the main workload")
     ap.add_argument("--schedule", default="auto",
@@ -510,6 +545,13 @@ def main():
         r4 = gpu_leg(w4, a.steps, a.warmup, a.schedule, ("fp64",))
         others["order4"] = dict(workload=workload_label(w4), zones=Z, **{k: summary(v) for k, v in r4.items()})
         del w4
+    if not a.no_amr and a.space_order == 2 and a.node_type == "lobatto" and shape is None and w["dim"] == 3:
+        patches = [((32, 40, 48), (64, 64, 64)), ((150, 130, 120), (48, 64, 80))]
+        print("[bench] refined patches", file=sys.stderr, flush=True)
+        r = run_amr(w, patches, a.steps, a.warmup)
+        others["amr"] = dict(workload=workload_label(w) + " coarse level, patches refined by 2 with subcycling", **r)
+        print(f"[bench] refined patches: {r['zone_updates']:.4e} zone-updates/s ({r['ms_per_step']:.1f} ms per "
+              f"coarse step)", file=sys.stderr, flush=True)
     if not a.no_boxes and shape is None:
         print("[bench] generating batched boxes", file=sys.stderr, flush=True)
         wb = si.boxes_workload()

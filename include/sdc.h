@@ -155,6 +155,49 @@ typedef struct {
   double* C[SDC_MAX_NODES - 2];
 } sdc_nodes;
 
+/*
+ * Two-level hierarchy: refined patches with subcycling in time around the
+ * SDC step (the extension to adaptive mesh refinement that Sec. 2 and Sec. 5
+ * name).  Level 0 is the periodic coarse grid of `coarse`; every patch is a
+ * box of coarse zones (lo, ext per direction, x y z; inside the grid, two or
+ * more coarse zones from every other patch) refined by 2 in space and time.
+ * Patch arrays are padded by 2 ghost zones per side and concatenated in patch
+ * order, each x fastest, SoA [n_c][Zf] (the layout of batched boxes with
+ * extents 2 ext + 4).  A coarse step of length dt: the coarse level takes one
+ * SDC step on every zone; each patch takes two steps of dt / 2 whose ghost
+ * zones are filled before every evaluation of A from the coarse node states
+ * of this step's last iteration (Lagrange polynomial through the node times
+ * in time, conservative piecewise-linear with central coarse slopes in space),
+ * with A zero in the ghost zones; the time-integrated fluxes of the last
+ * sweep through the coarse-fine faces are accumulated on both levels; the
+ * uncovered coarse zones next to a patch are refluxed with the averaged fine
+ * fluxes, and every covered coarse zone takes the mean of its fine zones.
+ * Composite-grid mass, momentum and total energy are conserved to rounding.
+ * Requirements: nbox = 0 and space_order = 2 in `coarse`.  Errors of
+ * sdc_amr_create come from sdc_last_error(NULL); later errors from
+ * sdc_last_error of the coarse handle (sdc_amr_handles).
+ */
+typedef struct sdc_amr_s* sdc_amr;
+typedef struct {
+  int32_t npatch;
+  const int64_t* lo;   /* [npatch][3] first covered coarse zone (x, y, z; entries beyond dim ignored) */
+  const int64_t* ext;  /* [npatch][3] covered coarse zones per direction */
+} sdc_patches;
+
+int sdc_amr_create(const sdc_config* coarse, const sdc_network* net, const sdc_patches* patches, sdc_amr* out);
+int sdc_amr_destroy(sdc_amr a);
+/* Zones of the coarse grid and of all padded patches together. */
+int sdc_amr_sizes(sdc_amr a, int64_t* zc, int64_t* zf);
+/* The two handles (coarse, and the patches as batched boxes): statistics,
+ * profiling and errors of the levels.  Owned by the hierarchy. */
+int sdc_amr_handles(sdc_amr a, sdc_handle* coarse, sdc_handle* fine);
+/* Every patch zone, ghosts included, from the coarse state Uc by the
+ * conservative piecewise-linear interpolation (initial data).  Synchronises. */
+int sdc_amr_fill_patches(sdc_amr a, const double* Uc, double* Uf, void* stream);
+/* nsteps coarse steps of length dt; Uc [n_c][Zc] and Uf [n_c][Zf] are
+ * updated in place (node arrays are owned by the hierarchy). */
+int sdc_amr_step(sdc_amr a, double dt, int32_t nsteps, double* Uc, double* Uf, void* stream);
+
 /* Fill `cfg` with defaults: 3 nodes, K = 4, FP64, MC slopes, local Rusanov
  * speed, gamma 1.4, tol 1e-13, maxiter 50, pivot threshold 0.1, no boxes,
  * plain launches. */

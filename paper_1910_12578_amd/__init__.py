@@ -4,4 +4,4 @@
 source R(U), the per-zone Newton reaction solve, the node-to-node SDC sweep and
 whole time steps, all computed by HIP kernels on the GPU.
 """
-from ._binding import SDC, SDCError, SDC_FP64, SDC_MIXED, config_from_workload  # noqa: F401
+from ._binding import AMR, SDC, SDCError, SDC_FP64, SDC_MIXED, config_from_workload  # noqa: F401

@@ -26,7 +26,8 @@ EXPORTS = ("sdc_config_default", "sdc_init", "sdc_destroy", "sdc_last_error", "s
            "sdc_stats", "sdc_check", "sdc_stats_reset", "sdc_set_params", "sdc_compile_only",
            "sdc_generated_source", "sdc_aot_name", "sdc_profile_enable", "sdc_profile_read", "sdc_cost_model",
            "sdc_step_adjoint", "sdc_set_schedule", "sdc_get_schedule", "sdc_autotune",
-           "sdc_reaction_solve_noalloc")
+           "sdc_reaction_solve_noalloc", "sdc_amr_create", "sdc_amr_destroy", "sdc_amr_sizes", "sdc_amr_handles",
+           "sdc_amr_fill_patches", "sdc_amr_step")
 KINDS = ("advect", "source", "solve", "transition_first", "transition_node0", "transition_later", "fill",
          "adjoint", "finish", "split", "order4")
 
@@ -51,6 +52,10 @@ class Config(ctypes.Structure):
                 ("pivot_threshold", c_double), ("nbox", c_int32), ("box_n", POINTER(c_int64)),
                 ("graph", c_int32), ("autotune", c_int32), ("node_type", c_int32),
                 ("space_order", c_int32)]
+
+
+class Patches(ctypes.Structure):
+    _fields_ = [("npatch", c_int32), ("lo", POINTER(c_int64)), ("ext", POINTER(c_int64))]
 
 
 class Nodes(ctypes.Structure):
@@ -83,6 +88,12 @@ def lib():
                                          c_void_p, c_void_p]
         L.sdc_reaction_solve_noalloc.argtypes = [c_void_p, c_double, c_int64, c_void_p, c_void_p, c_void_p,
                                                  c_void_p, c_void_p, c_void_p]
+        L.sdc_amr_create.argtypes = [POINTER(Config), POINTER(Network), POINTER(Patches), POINTER(c_void_p)]
+        L.sdc_amr_destroy.argtypes = [c_void_p]
+        L.sdc_amr_sizes.argtypes = [c_void_p, POINTER(c_int64), POINTER(c_int64)]
+        L.sdc_amr_handles.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p)]
+        L.sdc_amr_fill_patches.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+        L.sdc_amr_step.argtypes = [c_void_p, c_double, c_int32, c_void_p, c_void_p, c_void_p]
         L.sdc_sweep.argtypes = [c_void_p, c_double, c_int32, POINTER(Nodes), c_void_p]
         L.sdc_step.argtypes = [c_void_p, c_double, c_int32, c_void_p, POINTER(Nodes), c_void_p]
         L.sdc_stats.argtypes = [c_void_p, POINTER(c_int64)]
@@ -403,3 +414,65 @@ class SDC:
         if lnA.size != self.nreact or E.size != self.nreact:
             raise ValueError("expected one lnA and one E per reaction")
         _check(lib().sdc_set_params(self._h, _dptr(lnA), _dptr(E)), self._h)
+
+
+class AMR:
+    """Two-level hierarchy (refined patches with subcycling) on the current
+    GPU: wraps an sdc_amr.  `patches` is a list of (lo, ext) in coarse zones,
+    x first."""
+
+    def __init__(self, cfg: dict, net: dict, patches):
+        c = make_config(cfg)
+        n, keep = make_network(net)
+        lo = np.zeros((len(patches), 3), dtype=np.int64)
+        ext = np.ones((len(patches), 3), dtype=np.int64)
+        for i, (pl, pe) in enumerate(patches):
+            lo[i, :len(pl)] = pl
+            ext[i, :len(pe)] = pe
+        pt = Patches(len(patches), lo.ctypes.data_as(POINTER(c_int64)), ext.ctypes.data_as(POINTER(c_int64)))
+        a = c_void_p()
+        _check(lib().sdc_amr_create(byref(c), byref(n), byref(pt), byref(a)))
+        self._a = a
+        zc, zf = c_int64(), c_int64()
+        lib().sdc_amr_sizes(a, byref(zc), byref(zf))
+        self.zc, self.zf = zc.value, zf.value
+        hc, hf = c_void_p(), c_void_p()
+        lib().sdc_amr_handles(a, byref(hc), byref(hf))
+        self._hc, self._hf = hc, hf
+        self.ncomp = 2 + int(cfg["dim"]) + int(net["nspec"])
+
+    def _arr(self, t, zones):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+            raise TypeError("expected a contiguous float64 CUDA tensor")
+        if t.numel() != self.ncomp * zones:
+            raise ValueError(f"expected {self.ncomp} x {zones} elements, got {tuple(t.shape)}")
+        return c_void_p(t.data_ptr())
+
+    def fill_patches(self, Uc, Uf, stream=None):
+        _check(lib().sdc_amr_fill_patches(self._a, self._arr(Uc, self.zc), self._arr(Uf, self.zf),
+                                          SDC._stream(stream)), self._hc)
+
+    def step(self, dt, nsteps, Uc, Uf, stream=None):
+        _check(lib().sdc_amr_step(self._a, float(dt), int(nsteps), self._arr(Uc, self.zc), self._arr(Uf, self.zf),
+                                  SDC._stream(stream)), self._hc)
+
+    def stats(self):
+        out = []
+        for h in (self._hc, self._hf):
+            v = (c_int64 * NSTATS)()
+            _check(lib().sdc_stats(h, v), h)
+            v = list(v)
+            out.append(dict(hist=v[0:16], failed=v[16], iters=v[17], nonfinite=v[18], solves=v[19]))
+        return out
+
+    def close(self):
+        if getattr(self, "_a", None):
+            lib().sdc_amr_destroy(self._a)
+            self._a = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

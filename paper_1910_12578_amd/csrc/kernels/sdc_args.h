@@ -146,6 +146,68 @@ typedef struct {
   double gm1;
 } O4Args;
 
+// Two-level hierarchy (refined patches with subcycling): ghost-zone fills
+// of the padded patches from coarse node states, face-flux registers at the
+// coarse-fine interfaces, refluxing and average-down.
+typedef struct {
+  sdc_i64 zf;  // fine zone (index in the concatenated padded patches)
+  int pc[3];   // parent coarse zone coordinates
+  int sig;     // bit e set: the fine centre is +1/4 coarse zone from the parent's along e, else -1/4
+} AmrGhost;
+
+typedef struct {
+  double* Uf;                      // fine array [NC][Zf] (state to fill, or A to zero)
+  const double* Uc[SDC_MAXNODE];   // coarse node states [NC][Zc]
+  double w[SDC_MAXNODE];           // Lagrange weights of the coarse nodes at the fill time
+  int nnodes;
+  const AmrGhost* list;
+  sdc_i64 count;
+  sdc_i64 Zc, Zf;
+  int nc[3];                       // coarse extents
+} AmrFillArgs;
+
+typedef struct {
+  sdc_i64 base;  // zone offset of the grid (0: coarse; the box offset for a patch)
+  int c[3];      // coordinates of the zone whose i+1/2 face this is
+  int n[3];      // grid extents (periodic)
+  int d;         // face normal
+} AmrFace;
+
+typedef struct {
+  const double* U;
+  double* reg;   // [NC][count] += coef * F
+  const AmrFace* faces;
+  sdc_i64 count, Z;
+  double coef, gamma, alpha;
+  int slope;
+} AmrFluxArgs;
+
+typedef struct {
+  sdc_i64 zu;     // uncovered coarse zone next to a patch
+  sdc_i64 fc;     // its coarse face register
+  sdc_i64 ff[4];  // the fine face registers over that face (1, 2 or 4)
+  double sign;    // -1: the face is the zone's i+1/2 face, +1: its i-1/2 face
+  double h;       // coarse zone width along the face normal
+} AmrReflux;
+
+typedef struct {
+  sdc_i64 zc;      // covered coarse zone
+  sdc_i64 f0;      // its first fine zone
+  sdc_i64 sy, sz;  // fine zone strides along y and z
+} AmrCover;
+
+typedef struct {
+  double* Uc;
+  const double* Uf;
+  const double* regc;
+  const double* regf;
+  sdc_i64 Zc, Zf, nregc, nregf;
+  const AmrReflux* reflux;
+  sdc_i64 nreflux;
+  const AmrCover* cover;
+  sdc_i64 ncover;
+} AmrSyncArgs;
+
 typedef struct {
   double* p;
   sdc_i64 n;

@@ -1408,6 +1408,125 @@ extern "C" __global__ __launch_bounds__(256) void sdc_average_store4(O4Args a) {
   }
 }
 
+// ------------------------------------------------------------ refined patches
+// Two-level hierarchy around the SDC step (extension to refinement with
+// subcycling, Sec. 2 and Sec. 5): the patches are padded boxes whose G = 2
+// ghost zones are filled from the coarse level before every evaluation of A,
+// interpolated in time with the Lagrange weights of the coarse nodes and in
+// space conservatively and piecewise-linearly (central coarse slopes).
+
+__device__ __forceinline__ i64 coarse_zone(const int* c, const int* n, int e, int o) {
+  int q[3] = {c[0], c[1], c[2]};
+  q[e] += o;
+  q[e] = q[e] < 0 ? q[e] + n[e] : (q[e] >= n[e] ? q[e] - n[e] : q[e]);
+  return (i64)q[0] + (i64)n[0] * ((i64)q[1] + (i64)n[1] * q[2]);
+}
+
+// time-interpolated coarse value of component array offset `off` at zone z
+__device__ __forceinline__ double coarse_at(const AmrFillArgs& a, i64 off, i64 z) {
+  double v = 0.0;
+  for (int j = 0; j < a.nnodes; ++j) v += a.w[j] * a.Uc[j][off + z];
+  return v;
+}
+
+extern "C" __global__ __launch_bounds__(256) void sdc_amr_fill(AmrFillArgs a) {
+  const i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.count) return;
+  const AmrGhost e = a.list[g];
+  const i64 zp = coarse_zone(e.pc, a.nc, 0, 0);
+  for (int q = 0; q < SDC_NC; ++q) {
+    const i64 off = (i64)q * a.Zc;
+    double v = coarse_at(a, off, zp);
+#pragma unroll
+    for (int d = 0; d < SDC_DIM; ++d) {
+      const double slope = 0.5 * (coarse_at(a, off, coarse_zone(e.pc, a.nc, d, 1)) -
+                                  coarse_at(a, off, coarse_zone(e.pc, a.nc, d, -1)));
+      v += ((e.sig >> d) & 1 ? 0.25 : -0.25) * slope;
+    }
+    a.Uf[(i64)q * a.Zf + e.zf] = v;
+  }
+}
+
+// A = 0 in the ghost zones (their transitions are then reaction-only)
+extern "C" __global__ __launch_bounds__(256) void sdc_amr_zero(AmrFillArgs a) {
+  const i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.count) return;
+  const i64 z = a.list[g].zf;
+  for (int q = 0; q < SDC_NC; ++q) a.Uf[(i64)q * a.Zf + z] = 0.0;
+}
+
+// Face flux (the reconstruction and Rusanov flux of the advective term) at
+// listed faces, accumulated into a register: reg += coef * F.
+template <int D>
+__device__ __forceinline__ void amr_face_flux(const AmrFluxArgs& a, const AmrFace& f, i64 g) {
+  i64 z[4];
+#pragma unroll
+  for (int o = 0; o < 4; ++o) z[o] = f.base + coarse_zone(f.c, f.n, D, o - 1);
+  double WL[SDC_NH], WR[SDC_NH], F[SDC_NH];
+  auto states = [&](int q, double& L, double& R) {
+    const double* u = a.U + (i64)q * a.Z;
+    const double um = u[z[0]], u0 = u[z[1]], u1 = u[z[2]], u2 = u[z[3]];
+    L = u0 + 0.5 * slope_of(um, u0, u1, a.slope);
+    R = u1 - 0.5 * slope_of(u0, u1, u2, a.slope);
+  };
+#pragma unroll
+  for (int q = 0; q < SDC_NH; ++q) states(q, WL[q], WR[q]);
+  FaceHydro fh;
+  hydro_face(WL, WR, D, a.gamma, a.alpha, F, fh);
+#pragma unroll
+  for (int q = 0; q < SDC_NH; ++q) a.reg[(i64)q * a.count + g] += a.coef * F[q];
+  for (int s = 0; s < SDC_NS; ++s) {
+    double L, R;
+    states(SDC_NH + s, L, R);
+    a.reg[(i64)(SDC_NH + s) * a.count + g] += a.coef * species_face(L, R, fh);
+  }
+}
+
+extern "C" __global__ __launch_bounds__(256) void sdc_amr_flux(AmrFluxArgs a) {
+  const i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.count) return;
+  const AmrFace f = a.faces[g];
+  if (f.d == 0) amr_face_flux<0>(a, f, g);
+#if SDC_DIM >= 2
+  else if (f.d == 1) amr_face_flux<1>(a, f, g);
+#endif
+#if SDC_DIM >= 3
+  else amr_face_flux<2>(a, f, g);
+#endif
+}
+
+// Refluxing: the uncovered coarse zones next to a patch replace the coarse
+// flux through the shared face by the fine fluxes averaged over it.
+extern "C" __global__ __launch_bounds__(256) void sdc_amr_reflux(AmrSyncArgs a) {
+  const i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.nreflux) return;
+  const AmrReflux r = a.reflux[g];
+  for (int q = 0; q < SDC_NC; ++q) {
+    const double* ff = a.regf + (i64)q * a.nregf;
+    double f;
+    if (SDC_DIM == 1) f = ff[r.ff[0]];
+    else if (SDC_DIM == 2) f = 0.5 * (ff[r.ff[0]] + ff[r.ff[1]]);
+    else f = 0.5 * (0.5 * (ff[r.ff[0]] + ff[r.ff[1]]) + 0.5 * (ff[r.ff[2]] + ff[r.ff[3]]));
+    const double corr = (f - a.regc[(i64)q * a.nregc + r.fc]) / r.h;
+    a.Uc[(i64)q * a.Zc + r.zu] += r.sign * corr;
+  }
+}
+
+// Average-down: every covered coarse zone takes the mean of its fine zones.
+extern "C" __global__ __launch_bounds__(256) void sdc_amr_average(AmrSyncArgs a) {
+  const i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.ncover) return;
+  const AmrCover c = a.cover[g];
+  for (int q = 0; q < SDC_NC; ++q) {
+    const double* u = a.Uf + (i64)q * a.Zf + c.f0;
+    double acc = 0.0;
+    for (int cz = 0; cz < (SDC_DIM >= 3 ? 2 : 1); ++cz)
+      for (int cy = 0; cy < (SDC_DIM >= 2 ? 2 : 1); ++cy)
+        for (int cx = 0; cx < 2; ++cx) acc += u[cz * c.sz + cy * c.sy + cx];
+    a.Uc[(i64)q * a.Zc + c.zc] = acc / (double)(1 << SDC_DIM);
+  }
+}
+
 extern "C" __global__ void sdc_reset_counter(unsigned* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0u;
 }

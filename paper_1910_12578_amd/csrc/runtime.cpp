@@ -340,7 +340,7 @@ int prepare(const sdc_config* cfg, const sdc_network* net, Prepared* P, std::str
       int64_t zb = 1;
       for (int d = 0; d < 3; ++d) {
         const int64_t e = d < c.dim ? c.box_n[3 * bx + d] : 1;
-        if (e < minn || e > (int64_t(1) << 20)) {
+        if (d < c.dim && (e < minn || e > (int64_t(1) << 20))) {
           *err = "box extents must be in [2, 2^20] per direction (>= 1 without advection)";
           return SDC_ERR_ARG;
         }
@@ -966,8 +966,16 @@ int transition4(sdc_handle h, int kind, TransArgs a, hipStream_t s) {
   return launch(h, h->f_avgst4, h->P.Z, &o, s);
 }
 
+// Work a refined level inserts into a sweep: after each transition
+// (node m's new state, before its advective term) and after that term.
+struct SweepHooks {
+  virtual int after_state(int node, const sdc_nodes& n, hipStream_t s) const = 0;
+  virtual int after_advect(int node, const sdc_nodes& n, hipStream_t s) const = 0;
+  virtual ~SweepHooks() = default;
+};
+
 // One iteration k -> k+1 over the M transitions, then A at node M.
-int sweep(sdc_handle h, double dt, int k, const sdc_nodes& n, hipStream_t s) {
+int sweep(sdc_handle h, double dt, int k, const sdc_nodes& n, hipStream_t s, const SweepHooks* hooks = nullptr) {
   const int M = h->M;
   if (int rc = ensure_queue(h)) return rc;
   for (int m = 0; m < M; ++m) {
@@ -1014,9 +1022,11 @@ int sweep(sdc_handle h, double dt, int k, const sdc_nodes& n, hipStream_t s) {
       if ((rc = launch(h, f, h->P.Z, &a, s))) return rc;
       if ((rc = launch(h, h->f_trans_finish, std::min<int64_t>(h->P.Z, kFinishThreads), &a, s))) return rc;
     }
+    if (hooks && (rc = hooks->after_state(m + 1, n, s))) return rc;
     if (h->P.cfg.advection) {
       rc = advect(h, n.U[m + 1], n.A[m + 1], s);
       if (rc) return rc;
+      if (hooks && (rc = hooks->after_advect(m + 1, n, s))) return rc;
     }
   }
   return SDC_OK;
@@ -1902,6 +1912,516 @@ int sdc_cost_model(sdc_handle h, int64_t* out) {
   out[4] = f.exps;
   out[5] = h->P.pat.nnz_jac;
   out[6] = h->P.pat.nnz;
+  return SDC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- refined patches
+// Two-level hierarchy around the SDC step: a periodic coarse handle and a
+// handle over the padded patches (batched boxes, each box a patch refined by
+// 2 with 2 ghost zones per side).  A coarse step: the coarse level steps; each
+// patch takes two steps of dt/2 with ghost zones filled from the coarse node
+// states before every evaluation of A and A zeroed in the ghost zones; the
+// time-integrated fluxes through the coarse-fine faces are accumulated on both
+// levels during the last sweep; then refluxing and average-down.
+
+struct sdc_amr_s {
+  sdc_handle c = nullptr, f = nullptr;
+  int dim = 1, M = 1;
+  std::vector<int64_t> lo, ext;        // [np][3]
+  std::vector<int64_t> fbase;          // zone offset of each padded patch
+  sdc_nodes nc{}, nf{};                // node arrays of both levels (owned)
+  std::vector<double*> bufs;
+  AmrGhost* d_ghost = nullptr;
+  int64_t nghost = 0;
+  AmrFace *d_facec = nullptr, *d_facef = nullptr;
+  int64_t nfacec = 0, nfacef = 0;
+  double *regc = nullptr, *regf = nullptr;
+  AmrReflux* d_reflux = nullptr;
+  int64_t nreflux = 0;
+  AmrCover* d_cover = nullptr;
+  int64_t ncover = 0;
+  hipFunction_t f_fill = nullptr, f_zero = nullptr, f_flux = nullptr, f_reflux = nullptr, f_average = nullptr;
+};
+
+namespace {
+
+constexpr int kRatio = 2, kGhost = 2;
+
+template <class T>
+int upload(sdc_handle h, const std::vector<T>& v, T** out) {
+  if (v.empty()) return SDC_OK;
+  if (hipMalloc((void**)out, v.size() * sizeof(T)) != hipSuccess)
+    return fail(h, SDC_ERR_NOMEM, "hipMalloc(hierarchy tables) failed");
+  HIP_CHECK(h, hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return SDC_OK;
+}
+
+int amr_alloc_nodes(sdc_amr a, sdc_handle h, sdc_nodes* n) {
+  std::memset(n, 0, sizeof *n);
+  const size_t Z = (size_t)h->P.Z;
+  auto get = [&](int comps, double** p) {
+    if (hipMalloc((void**)p, comps * Z * sizeof(double)) != hipSuccess) return false;
+    a->bufs.push_back(*p);
+    return true;
+  };
+  for (int j = 0; j <= h->M; ++j)
+    if (!get(h->nc, &n->U[j]) || !get(h->nc, &n->A[j]) || !get(h->nx, &n->R[j]))
+      return fail(h, SDC_ERR_NOMEM, "hipMalloc(hierarchy node arrays) failed");
+  for (int j = 0; j + 1 < h->M; ++j)
+    if (!get(h->nc, &n->C[j])) return fail(h, SDC_ERR_NOMEM, "hipMalloc(hierarchy node arrays) failed");
+  return SDC_OK;
+}
+
+// Lagrange weights of the node times tau at theta.
+void lagrange(const std::vector<double>& tau, double theta, double* w) {
+  for (size_t i = 0; i < tau.size(); ++i) {
+    w[i] = 1.0;
+    for (size_t j = 0; j < tau.size(); ++j)
+      if (j != i) w[i] *= (theta - tau[j]) / (tau[i] - tau[j]);
+  }
+}
+
+int amr_launch(sdc_handle h, hipFunction_t f, int64_t n, void* args, hipStream_t s) { return launch(h, f, n, args, s); }
+
+// Fill the ghost zones (or, all_zones, every zone) of the fine array U at
+// coarse-step fraction theta from the coarse node states.
+int amr_fill(sdc_amr a, double* U, double theta, hipStream_t s) {
+  AmrFillArgs f;
+  std::memset(&f, 0, sizeof f);
+  f.Uf = U;
+  for (int j = 0; j <= a->M; ++j) f.Uc[j] = a->nc.U[j];
+  lagrange(a->c->tau, theta, f.w);
+  f.nnodes = a->M + 1;
+  f.list = a->d_ghost;
+  f.count = a->nghost;
+  f.Zc = a->c->P.Z;
+  f.Zf = a->f->P.Z;
+  for (int d = 0; d < 3; ++d) f.nc[d] = d < a->dim ? (int)a->c->P.cfg.n[d] : 1;
+  return amr_launch(a->c, a->f_fill, a->nghost, &f, s);
+}
+
+int amr_zero(sdc_amr a, double* A, hipStream_t s) {
+  AmrFillArgs f;
+  std::memset(&f, 0, sizeof f);
+  f.Uf = A;
+  f.list = a->d_ghost;
+  f.count = a->nghost;
+  f.Zf = a->f->P.Z;
+  return amr_launch(a->c, a->f_zero, a->nghost, &f, s);
+}
+
+int amr_flux(sdc_amr a, sdc_handle h, const double* U, double* reg, const AmrFace* faces, int64_t n, double coef,
+             hipStream_t s) {
+  if (!h->P.cfg.advection || n == 0 || coef == 0.0) return SDC_OK;
+  AmrFluxArgs f;
+  std::memset(&f, 0, sizeof f);
+  f.U = U;
+  f.reg = reg;
+  f.faces = faces;
+  f.count = n;
+  f.Z = h->P.Z;
+  f.coef = coef;
+  f.gamma = h->P.cfg.gamma;
+  f.alpha = h->P.cfg.alpha;
+  f.slope = h->P.cfg.slope;
+  return amr_launch(a->c, a->f_flux, n, &f, s);
+}
+
+// Ghost fills and ghost-zone A of a patch sweep in substep `sub`.
+struct PatchHooks : SweepHooks {
+  sdc_amr a;
+  int sub;
+  PatchHooks(sdc_amr a_, int s_) : a(a_), sub(s_) {}
+  int after_state(int node, const sdc_nodes& n, hipStream_t s) const override {
+    return amr_fill(a, n.U[node], (sub + a->f->tau[node]) / kRatio, s);
+  }
+  int after_advect(int node, const sdc_nodes& n, hipStream_t s) const override { return amr_zero(a, n.A[node], s); }
+};
+
+// One SDC step of a level from U into its node arrays, with the flux
+// register accumulated in the last sweep:
+//   reg += dt sum_j w_j F(U^{j,(K-1)}) + sum_{m=1}^{M-1} dt_m (F(U^{m,(K)}) - F(U^{m,(K-1)})).
+int amr_level_step(sdc_amr a, sdc_handle h, const sdc_nodes& n, const double* U, double dt, const SweepHooks* hooks,
+                   double* reg, const AmrFace* faces, int64_t nfaces, hipStream_t s) {
+  const size_t bytes = (size_t)h->nc * h->P.Z * sizeof(double);
+  HIP_CHECK(h, hipMemcpyAsync(n.U[0], U, bytes, hipMemcpyDeviceToDevice, s));
+  int rc;
+  if (hooks && (rc = hooks->after_state(0, n, s))) return rc;
+  if ((rc = advect(h, n.U[0], n.A[0], s))) return rc;
+  if (hooks && h->P.cfg.advection && (rc = hooks->after_advect(0, n, s))) return rc;
+  if ((rc = source(h, n.U[0], n.R[0], s))) return rc;
+  if (!h->P.cfg.advection)
+    for (int j = 1; j <= h->M; ++j)
+      if ((rc = fill(h, n.A[j], (int64_t)h->nc * h->P.Z, 0.0, s))) return rc;
+  const int K = h->P.cfg.n_iters, M = h->M;
+  std::vector<double> w(M + 1, 0.0), dtm(M, 0.0);
+  for (int m = 0; m < M; ++m) {
+    dtm[m] = (h->tau[m + 1] - h->tau[m]) * dt;
+    for (int j = 0; j <= M; ++j) w[j] += h->S[m][j];
+  }
+  for (int k = 0; k < K; ++k) {
+    if (k == K - 1) {
+      for (int j = 0; j <= M; ++j) {
+        const double coef = dt * w[j] - (j >= 1 && j < M ? dtm[j] : 0.0);
+        if ((rc = amr_flux(a, h, k == 0 ? n.U[0] : n.U[j], reg, faces, nfaces, coef, s))) return rc;
+      }
+    }
+    if ((rc = sweep(h, dt, k, n, s, hooks))) return rc;
+  }
+  for (int m = 1; m < M; ++m)
+    if ((rc = amr_flux(a, h, n.U[m], reg, faces, nfaces, dtm[m], s))) return rc;
+  return SDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sdc_amr_create(const sdc_config* coarse, const sdc_network* net, const sdc_patches* patches, sdc_amr* out) {
+  if (!out || !coarse || !net || !patches) return fail(nullptr, SDC_ERR_ARG, "null argument");
+  *out = nullptr;
+  const sdc_config& cc = *coarse;
+  if (cc.nbox != 0 || cc.space_order != 2 || cc.dim < 1 || cc.dim > 3)
+    return fail(nullptr, SDC_ERR_UNSUPPORTED, "a hierarchy needs a single periodic coarse grid and space_order 2");
+  const int np = patches->npatch, dim = cc.dim;
+  if (np < 1 || !patches->lo || !patches->ext) return fail(nullptr, SDC_ERR_ARG, "need at least one patch");
+  for (int p = 0; p < np; ++p)
+    for (int d = 0; d < dim; ++d) {
+      const int64_t l = patches->lo[3 * p + d], e = patches->ext[3 * p + d];
+      if (e < 1 || l < 0 || l + e > cc.n[d]) return fail(nullptr, SDC_ERR_ARG, "patch must lie inside the coarse grid");
+    }
+  for (int p = 0; p < np; ++p)
+    for (int q = p + 1; q < np; ++q) {
+      bool apart = false;
+      for (int d = 0; d < dim; ++d) {
+        const int64_t lp = patches->lo[3 * p + d], ep = patches->ext[3 * p + d];
+        const int64_t lq = patches->lo[3 * q + d], eq = patches->ext[3 * q + d];
+        apart = apart || lp + ep + 2 <= lq || lq + eq + 2 <= lp;
+      }
+      if (!apart) return fail(nullptr, SDC_ERR_ARG, "patches must be two or more coarse zones apart");
+    }
+  auto* a = new (std::nothrow) sdc_amr_s;
+  if (!a) return fail(nullptr, SDC_ERR_NOMEM, "host allocation failed");
+  a->dim = dim;
+  a->lo.assign(patches->lo, patches->lo + 3 * np);
+  a->ext.assign(patches->ext, patches->ext + 3 * np);
+  int rc = sdc_init(coarse, net, &a->c);
+  if (rc) {
+    delete a;
+    return rc;
+  }
+  // the fine handle: the padded patches as batched boxes, half the zone width
+  std::vector<int64_t> box(3 * np, 1);
+  for (int p = 0; p < np; ++p)
+    for (int d = 0; d < dim; ++d) box[3 * p + d] = kRatio * a->ext[3 * p + d] + 2 * kGhost;
+  sdc_config fc = cc;
+  for (int d = 0; d < 3; ++d) fc.dx[d] = cc.dx[d] / kRatio;
+  fc.nbox = np;
+  fc.box_n = box.data();
+  fc.graph = 0;
+  auto bail = [&](int code) {
+    sdc_amr_destroy(a);
+    return code;
+  };
+  if ((rc = sdc_init(&fc, net, &a->f))) {
+    const std::string msg = g_init_error;
+    sdc_amr_destroy(a);
+    return fail(nullptr, rc, "fine level: " + msg);
+  }
+  sdc_handle c = a->c, f = a->f;
+  a->M = c->M;
+  a->fbase.assign(f->P.box_off.begin(), f->P.box_off.end() - 1);
+  struct {
+    hipFunction_t* fn;
+    const char* name;
+  } fns[] = {{&a->f_fill, "sdc_amr_fill"}, {&a->f_zero, "sdc_amr_zero"}, {&a->f_flux, "sdc_amr_flux"},
+             {&a->f_reflux, "sdc_amr_reflux"}, {&a->f_average, "sdc_amr_average"}};
+  for (auto& fn : fns)
+    if (hipModuleGetFunction(fn.fn, c->mod, fn.name) != hipSuccess) {
+      fail(nullptr, SDC_ERR_HIP, std::string("missing kernel ") + fn.name);
+      return bail(SDC_ERR_HIP);
+    }
+  int ncx[3] = {1, 1, 1};
+  for (int d = 0; d < dim; ++d) ncx[d] = (int)cc.n[d];
+  // ghost zones, coarse and fine interface faces, reflux and cover tables
+  std::vector<AmrGhost> ghost;
+  std::vector<AmrFace> facec, facef;
+  std::vector<AmrReflux> reflux;
+  std::vector<AmrCover> cover;
+  for (int p = 0; p < np; ++p) {
+    int nb[3] = {1, 1, 1};
+    for (int d = 0; d < 3; ++d) nb[d] = (int)box[3 * p + d];
+    const int64_t base = a->fbase[p];
+    for (int k = 0; k < nb[2]; ++k)
+      for (int j = 0; j < nb[1]; ++j)
+        for (int i = 0; i < nb[0]; ++i) {
+          const int fi[3] = {i, j, k};
+          bool inner = true;
+          AmrGhost g;
+          g.zf = base + i + (int64_t)nb[0] * (j + (int64_t)nb[1] * k);
+          g.sig = 0;
+          for (int d = 0; d < 3; ++d) {
+            g.pc[d] = 0;
+            if (d >= dim) continue;
+            inner = inner && fi[d] >= kGhost && fi[d] < nb[d] - kGhost;
+            const int64_t gl = kRatio * a->lo[3 * p + d] + (fi[d] - kGhost);  // global fine index
+            int64_t par = gl >= 0 ? gl / kRatio : -((-gl + kRatio - 1) / kRatio);
+            if (gl - kRatio * par != 0) g.sig |= 1 << d;
+            par %= ncx[d];
+            if (par < 0) par += ncx[d];
+            g.pc[d] = (int)par;
+          }
+          if (!inner) ghost.push_back(g);
+        }
+    // interface faces: per direction and side, every transverse position
+    for (int d = 0; d < dim; ++d) {
+      const int64_t l = a->lo[3 * p + d], e = a->ext[3 * p + d];
+      const double h = cc.dx[d];
+      int t1 = -1, t2 = -1;  // transverse directions, ascending
+      for (int t = 0; t < dim; ++t)
+        if (t != d) (t1 < 0 ? t1 : t2) = t;
+      const int64_t n1 = t1 >= 0 ? a->ext[3 * p + t1] : 1, n2 = t2 >= 0 ? a->ext[3 * p + t2] : 1;
+      for (int side = 0; side < 2; ++side)
+        for (int64_t b2 = 0; b2 < n2; ++b2)
+          for (int64_t b1 = 0; b1 < n1; ++b1) {
+            AmrFace cf;
+            std::memset(&cf, 0, sizeof cf);
+            cf.base = 0;
+            for (int t = 0; t < 3; ++t) cf.n[t] = ncx[t];
+            cf.d = d;
+            int64_t ci = side == 0 ? l - 1 : l + e - 1;  // coarse zone whose i+1/2 face it is
+            ci = ((ci % ncx[d]) + ncx[d]) % ncx[d];
+            cf.c[d] = (int)ci;
+            if (t1 >= 0) cf.c[t1] = (int)(a->lo[3 * p + t1] + b1);
+            if (t2 >= 0) cf.c[t2] = (int)(a->lo[3 * p + t2] + b2);
+            AmrReflux r;
+            std::memset(&r, 0, sizeof r);
+            r.fc = (int64_t)facec.size();
+            facec.push_back(cf);
+            int uz[3] = {cf.c[0], cf.c[1], cf.c[2]};
+            uz[d] = (int)(side == 0 ? ((l - 1) % ncx[d] + ncx[d]) % ncx[d] : (l + e) % ncx[d]);
+            r.zu = uz[0] + (int64_t)ncx[0] * (uz[1] + (int64_t)ncx[1] * uz[2]);
+            r.sign = side == 0 ? -1.0 : 1.0;
+            r.h = h;
+            // the fine faces over it: pairs along t1 (inner) then t2
+            int q = 0;
+            for (int s2 = 0; s2 < (t2 >= 0 ? kRatio : 1); ++s2)
+              for (int s1 = 0; s1 < (t1 >= 0 ? kRatio : 1); ++s1) {
+                AmrFace ff;
+                std::memset(&ff, 0, sizeof ff);
+                ff.base = base;
+                for (int t = 0; t < 3; ++t) ff.n[t] = nb[t];
+                ff.d = d;
+                ff.c[d] = side == 0 ? kGhost - 1 : kGhost + (int)(kRatio * e) - 1;
+                if (t1 >= 0) ff.c[t1] = kGhost + (int)(kRatio * b1) + s1;
+                if (t2 >= 0) ff.c[t2] = kGhost + (int)(kRatio * b2) + s2;
+                r.ff[q++] = (int64_t)facef.size();
+                facef.push_back(ff);
+              }
+            reflux.push_back(r);
+          }
+    }
+    // covered coarse zones and their first fine zone
+    const int64_t e0 = a->ext[3 * p], e1 = dim > 1 ? a->ext[3 * p + 1] : 1, e2 = dim > 2 ? a->ext[3 * p + 2] : 1;
+    for (int64_t k = 0; k < e2; ++k)
+      for (int64_t j = 0; j < e1; ++j)
+        for (int64_t i = 0; i < e0; ++i) {
+          AmrCover cv;
+          const int64_t ci = a->lo[3 * p] + i, cj = dim > 1 ? a->lo[3 * p + 1] + j : 0,
+                        ck = dim > 2 ? a->lo[3 * p + 2] + k : 0;
+          cv.zc = ci + (int64_t)ncx[0] * (cj + (int64_t)ncx[1] * ck);
+          const int64_t fi = kGhost + kRatio * i, fj = dim > 1 ? kGhost + kRatio * j : 0,
+                        fk = dim > 2 ? kGhost + kRatio * k : 0;
+          cv.sy = nb[0];
+          cv.sz = (int64_t)nb[0] * nb[1];
+          cv.f0 = base + fi + cv.sy * fj + cv.sz * fk;
+          cover.push_back(cv);
+        }
+  }
+  // every table entry inside its arrays (the kernels index with them unchecked)
+  {
+    const int64_t Zc = c->P.Z, Zf = f->P.Z, nfc = (int64_t)facec.size(), nff = (int64_t)facef.size();
+    bool ok = true;
+    for (const AmrGhost& g : ghost) {
+      ok = ok && g.zf >= 0 && g.zf < Zf;
+      for (int d = 0; d < 3; ++d) ok = ok && g.pc[d] >= 0 && g.pc[d] < ncx[d];
+    }
+    auto face_ok = [&](const AmrFace& fa, int64_t Z, bool wrap) {
+      int64_t vol = 1;
+      bool r = fa.base >= 0;
+      for (int d = 0; d < 3; ++d) {
+        r = r && fa.c[d] >= 0 && fa.c[d] < fa.n[d] && fa.n[d] >= 1;
+        vol *= fa.n[d];
+      }
+      r = r && fa.d >= 0 && fa.d < dim && fa.base + vol <= Z && fa.n[fa.d] >= 2;
+      if (!wrap) r = r && fa.c[fa.d] - 1 >= 0 && fa.c[fa.d] + 2 < fa.n[fa.d];
+      return r;
+    };
+    for (const AmrFace& fa : facec) ok = ok && face_ok(fa, Zc, true);
+    for (const AmrFace& fa : facef) ok = ok && face_ok(fa, Zf, false);
+    for (const AmrReflux& r : reflux) {
+      ok = ok && r.zu >= 0 && r.zu < Zc && r.fc >= 0 && r.fc < nfc;
+      for (int q = 0; q < (1 << (dim - 1)); ++q) ok = ok && r.ff[q] >= 0 && r.ff[q] < nff;
+    }
+    for (const AmrCover& cv : cover)
+      ok = ok && cv.zc >= 0 && cv.zc < Zc && cv.f0 >= 0 &&
+           cv.f0 + (dim > 2 ? cv.sz : 0) + (dim > 1 ? cv.sy : 0) + 1 < Zf;
+    if (!ok) {
+      fail(nullptr, SDC_ERR_ARG, "hierarchy tables out of range");
+      return bail(SDC_ERR_ARG);
+    }
+  }
+  a->nghost = (int64_t)ghost.size();
+  a->nfacec = (int64_t)facec.size();
+  a->nfacef = (int64_t)facef.size();
+  a->nreflux = (int64_t)reflux.size();
+  a->ncover = (int64_t)cover.size();
+  if ((rc = upload(c, ghost, &a->d_ghost)) || (rc = upload(c, facec, &a->d_facec)) ||
+      (rc = upload(c, facef, &a->d_facef)) || (rc = upload(c, reflux, &a->d_reflux)) ||
+      (rc = upload(c, cover, &a->d_cover))) {
+    g_init_error = c->err;
+    return bail(rc);
+  }
+  if (hipMalloc((void**)&a->regc, std::max<int64_t>(1, a->nfacec) * c->nc * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&a->regf, std::max<int64_t>(1, a->nfacef) * c->nc * sizeof(double)) != hipSuccess) {
+    fail(nullptr, SDC_ERR_NOMEM, "hipMalloc(flux registers) failed");
+    return bail(SDC_ERR_NOMEM);
+  }
+  if ((rc = amr_alloc_nodes(a, c, &a->nc)) || (rc = amr_alloc_nodes(a, f, &a->nf))) {
+    g_init_error = rc == SDC_ERR_NOMEM ? "hipMalloc(hierarchy node arrays) failed" : c->err;
+    return bail(rc);
+  }
+  *out = a;
+  return SDC_OK;
+}
+
+int sdc_amr_destroy(sdc_amr a) {
+  if (!a) return SDC_OK;
+  (void)hipDeviceSynchronize();
+  for (double* p : a->bufs) (void)hipFree(p);
+  for (void* p : {(void*)a->d_ghost, (void*)a->d_facec, (void*)a->d_facef, (void*)a->regc, (void*)a->regf,
+                  (void*)a->d_reflux, (void*)a->d_cover})
+    if (p) (void)hipFree(p);
+  sdc_destroy(a->f);
+  sdc_destroy(a->c);
+  delete a;
+  return SDC_OK;
+}
+
+int sdc_amr_sizes(sdc_amr a, int64_t* zc, int64_t* zf) {
+  if (!a) return SDC_ERR_ARG;
+  if (zc) *zc = a->c->P.Z;
+  if (zf) *zf = a->f->P.Z;
+  return SDC_OK;
+}
+
+int sdc_amr_handles(sdc_amr a, sdc_handle* coarse, sdc_handle* fine) {
+  if (!a) return SDC_ERR_ARG;
+  if (coarse) *coarse = a->c;
+  if (fine) *fine = a->f;
+  return SDC_OK;
+}
+
+int sdc_amr_fill_patches(sdc_amr a, const double* Uc, double* Uf, void* stream) {
+  if (!a) return SDC_ERR_ARG;
+  if (!Uc || !Uf) return fail(a->c, SDC_ERR_ARG, "null array");
+  hipStream_t s = (hipStream_t)stream;
+  a->c->last_stream = s;
+  // every fine zone takes the interpolated coarse state: the ghost list
+  // covers ghost zones only, so fill with a list of all zones built here
+  std::vector<AmrGhost> all;
+  const int np = (int)a->fbase.size();
+  int ncx[3] = {1, 1, 1};
+  for (int d = 0; d < a->dim; ++d) ncx[d] = (int)a->c->P.cfg.n[d];
+  for (int p = 0; p < np; ++p) {
+    int nb[3] = {1, 1, 1};
+    for (int d = 0; d < a->dim; ++d) nb[d] = (int)(kRatio * a->ext[3 * p + d] + 2 * kGhost);
+    for (int k = 0; k < nb[2]; ++k)
+      for (int j = 0; j < nb[1]; ++j)
+        for (int i = 0; i < nb[0]; ++i) {
+          const int fi[3] = {i, j, k};
+          AmrGhost g;
+          g.zf = a->fbase[p] + i + (int64_t)nb[0] * (j + (int64_t)nb[1] * k);
+          g.sig = 0;
+          for (int d = 0; d < 3; ++d) {
+            g.pc[d] = 0;
+            if (d >= a->dim) continue;
+            const int64_t gl = kRatio * a->lo[3 * p + d] + (fi[d] - kGhost);
+            int64_t par = gl >= 0 ? gl / kRatio : -((-gl + kRatio - 1) / kRatio);
+            if (gl - kRatio * par != 0) g.sig |= 1 << d;
+            par = ((par % ncx[d]) + ncx[d]) % ncx[d];
+            g.pc[d] = (int)par;
+          }
+          all.push_back(g);
+        }
+  }
+  AmrGhost* d_all = nullptr;
+  if (int rc = upload(a->c, all, &d_all)) return rc;
+  AmrFillArgs f;
+  std::memset(&f, 0, sizeof f);
+  f.Uf = Uf;
+  f.Uc[0] = Uc;
+  f.w[0] = 1.0;
+  f.nnodes = 1;
+  f.list = d_all;
+  f.count = (int64_t)all.size();
+  f.Zc = a->c->P.Z;
+  f.Zf = a->f->P.Z;
+  for (int d = 0; d < 3; ++d) f.nc[d] = ncx[d];
+  int rc = amr_launch(a->c, a->f_fill, f.count, &f, s);
+  if (hipStreamSynchronize(s) != hipSuccess && rc == SDC_OK) rc = fail(a->c, SDC_ERR_HIP, "fill failed");
+  (void)hipFree(d_all);
+  return rc;
+}
+
+int sdc_amr_step(sdc_amr a, double dt, int32_t nsteps, double* Uc, double* Uf, void* stream) {
+  if (!a) return SDC_ERR_ARG;
+  sdc_handle c = a->c, f = a->f;
+  if (!Uc || !Uf || nsteps < 0) return fail(c, SDC_ERR_ARG, "null state or negative nsteps");
+  if (!std::isfinite(dt) || dt <= 0.0) return fail(c, SDC_ERR_ARG, "dt must be positive");
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = f->last_stream = s;
+  const size_t bc = (size_t)c->nc * c->P.Z * sizeof(double), bf = (size_t)f->nc * f->P.Z * sizeof(double);
+  int rc;
+  // autotune = 1: the coarse level's Newton schedule (cached on disk or
+  // tuned on Uc) serves both levels
+  if (nsteps > 0 && c->P.cfg.autotune && !c->tuned && !load_tuning(c)) {
+    if ((rc = autotune(c, dt, Uc, a->nc, s))) return rc;
+  }
+  f->occ2 = c->occ2;
+  f->cap = c->cap;
+  for (int step = 0; step < nsteps; ++step) {
+    if ((rc = fill(c, a->regc, a->nfacec * c->nc, 0.0, s)) || (rc = fill(c, a->regf, a->nfacef * c->nc, 0.0, s)))
+      return rc;
+    // coarse level: one step, its node states kept for the ghost fills
+    if ((rc = amr_level_step(a, c, a->nc, Uc, dt, nullptr, a->regc, a->d_facec, a->nfacec, s))) return rc;
+    // patches: two substeps of dt / 2
+    for (int sub = 0; sub < kRatio; ++sub) {
+      PatchHooks hooks(a, sub);
+      if ((rc = amr_level_step(a, f, a->nf, Uf, dt / kRatio, &hooks, a->regf, a->d_facef, a->nfacef, s))) return rc;
+      HIP_CHECK(f, hipMemcpyAsync(Uf, a->nf.U[a->M], bf, hipMemcpyDeviceToDevice, s));
+    }
+    // synchronisation: reflux the uncovered neighbours, average down
+    AmrSyncArgs y;
+    std::memset(&y, 0, sizeof y);
+    y.Uc = a->nc.U[a->M];
+    y.Uf = Uf;
+    y.regc = a->regc;
+    y.regf = a->regf;
+    y.Zc = c->P.Z;
+    y.Zf = f->P.Z;
+    y.nregc = a->nfacec;
+    y.nregf = a->nfacef;
+    y.reflux = a->d_reflux;
+    y.nreflux = c->P.cfg.advection ? a->nreflux : 0;
+    y.cover = a->d_cover;
+    y.ncover = a->ncover;
+    if ((rc = amr_launch(c, a->f_reflux, y.nreflux, &y, s)) || (rc = amr_launch(c, a->f_average, y.ncover, &y, s)))
+      return rc;
+    HIP_CHECK(c, hipMemcpyAsync(Uc, a->nc.U[a->M], bc, hipMemcpyDeviceToDevice, s));
+  }
   return SDC_OK;
 }
 
