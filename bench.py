@@ -83,8 +83,8 @@ def kernel_model(h, stats, dim):
 def kernel_model4(h, stats, dim):
     """Algorithmic bytes (and flops where counted) per zone of each kernel kind
     of the fourth-order method.  The advective term counts what an evaluation
-    must move (read U, write A: 2 n_c values), spread over its 2 dim launches
-    (a face-flux and a divergence kernel per direction); the transition kinds
+    must move (read U, write A: 2 n_c values), spread over its 3 dim launches
+    (face averages, face fluxes and their divergence per direction); the transition kinds
     are the right-hand-side kernels (state, advective, correction and source
     inputs, the rhs and the Newton guess out); `order4` averages the
     zone-centre Newton-input kernel (rhs in; rho_c and b_c out) and the average
@@ -96,7 +96,7 @@ def kernel_model4(h, stats, dim):
     per_iter = cm["residual_matrix"] + cm["lu"] + cm["solve"] + 2 * nx
     nu = stats["iters"] / max(stats["solves"] - stats["failed"], 1)
     words = {
-        "advect": 2 * nc / (2 * dim),
+        "advect": 2 * nc / (3 * dim),
         "transition_first": 4 * nc + nx,
         "transition_node0": 2 * nc + (M + 1) * (nc + nx) + (M - 1) * nc + nc + nx,
         "transition_later": 5 * nc + nx,
@@ -125,7 +125,7 @@ def roofline(bytes_per_zone, flops_per_zone, zones, avg_s):
 def kernel_name(kind, dim, sched, precision, order=2):
     """Name of the kernel that a profiled kind stands for under a schedule."""
     if order == 4:
-        return {"advect": "sdc_flux4_d+sdc_div4_d", "order4": "sdc_newton_inputs4+sdc_average_store4",
+        return {"advect": "sdc_faceavg4_d+sdc_flux4_d+sdc_div4_d", "order4": "sdc_newton_inputs4+sdc_average_store4",
                 "solve": "sdc_reaction_solve" + ("_o2" if sched["occ2"] else ""),
                 "source": "sdc_source4_centre+sdc_convert4"}.get(kind, "sdc_rhs4_" + kind.split("_")[-1])
     if kind == "advect":

@@ -116,6 +116,7 @@ typedef struct {
   const double* U;
   double* F;
   double* A;
+  double* Uf;  // face averages along the current direction [NC][Z] (face i+1/2 of every zone)
   sdc_i64 Z;
   int n[3];
   int first;

@@ -1168,11 +1168,25 @@ __device__ __forceinline__ i64 zone_off(const int* c, const int* n, int d0, int 
   return (i64)q[0] + (i64)n[0] * ((i64)q[1] + (i64)n[1] * q[2]);
 }
 
+// the 2 DIM neighbour zones (+d, -d per direction) of the zone at c
+struct Nbr {
+  i64 p[SDC_DIM], m[SDC_DIM];
+};
+__device__ __forceinline__ Nbr neighbours(const int* c, const int* n) {
+  Nbr b;
+#pragma unroll
+  for (int d = 0; d < SDC_DIM; ++d) {
+    b.p[d] = zone_off(c, n, d, 1, d, 0);
+    b.m[d] = zone_off(c, n, d, -1, d, 0);
+  }
+  return b;
+}
+
 // second differences of u summed over directions: sum_d (u_{+d} - 2 u) + u_{-d}
-__device__ __forceinline__ double lap_sum(const double* u, const int* c, const int* n, double u0) {
+__device__ __forceinline__ double lap_sum(const double* u, const Nbr& b, double u0) {
   double l = 0.0;
 #pragma unroll
-  for (int d = 0; d < SDC_DIM; ++d) l += (u[zone_off(c, n, d, 1, d, 0)] - 2.0 * u0) + u[zone_off(c, n, d, -1, d, 0)];
+  for (int d = 0; d < SDC_DIM; ++d) l += (u[b.p[d]] - 2.0 * u0) + u[b.m[d]];
   return l;
 }
 
@@ -1191,13 +1205,30 @@ __device__ __forceinline__ void transverse(int t, int& dd, int& o) {
   }
 }
 
-// face average along D at the face i+1/2 of the zone c shifted by o along dd
+// Face averages along D of every zone's face i+1/2, all components: a pass of
+// its own, so that the flux kernel reads each face average once per
+// transverse position instead of re-forming it from four zone averages.
 template <int D>
-__device__ __forceinline__ double face_avg4(const double* u, const int* c, const int* n, int dd, int o) {
-  const double a = u[zone_off(c, n, dd, o, D, 0)], b = u[zone_off(c, n, dd, o, D, 1)];
-  const double am = u[zone_off(c, n, dd, o, D, -1)], bp = u[zone_off(c, n, dd, o, D, 2)];
-  return (7.0 / 12.0) * (a + b) - (1.0 / 12.0) * (am + bp);
+__device__ __forceinline__ void faceavg4_body(const Flux4Args& a) {
+  const i64 z = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= a.Z) return;
+  int c[3];
+  zone_coords(z, a.n, c);
+  const i64 zm = zone_off(c, a.n, D, -1, D, 0), zp = zone_off(c, a.n, D, 1, D, 0), zpp = zone_off(c, a.n, D, 2, D, 0);
+  for (int q = 0; q < SDC_NC; ++q) {
+    const double* u = a.U + (i64)q * a.Z;
+    a.Uf[(i64)q * a.Z + z] = (7.0 / 12.0) * (u[z] + u[zp]) - (1.0 / 12.0) * (u[zm] + u[zpp]);
+  }
 }
+extern "C" __global__ __launch_bounds__(256) void sdc_faceavg4_0(Flux4Args a) { faceavg4_body<0>(a); }
+#if SDC_DIM >= 2
+extern "C" __global__ __launch_bounds__(256) void sdc_faceavg4_1(Flux4Args a) { faceavg4_body<1>(a); }
+#endif
+#if SDC_DIM >= 3
+extern "C" __global__ __launch_bounds__(256) void sdc_faceavg4_2(Flux4Args a) { faceavg4_body<2>(a); }
+#endif
+
+
 
 // 1/24 of the second differences across the face from the face values v[t]
 __device__ __forceinline__ double cross_lap24(const double* v) {
@@ -1218,12 +1249,17 @@ __device__ __forceinline__ void flux4_body(const Flux4Args& a) {
   // fluxes and velocities, the face-centre value and its flux
   double W[SDC_NT][SDC_NH], un[SDC_NT];
   double F[SDC_NH], Fc[SDC_NH], Wc[SDC_NH], unc, p, cs;
+  i64 zt[SDC_NT];  // zones of the transverse positions (the same for every component)
 #pragma unroll
   for (int t = 0; t < SDC_NT; ++t) {
     int dd, o;
     transverse<D>(t, dd, o);
+    zt[t] = zone_off(c, a.n, dd, o, dd, 0);
+  }
 #pragma unroll
-    for (int q = 0; q < SDC_NH; ++q) W[t][q] = face_avg4<D>(a.U + (i64)q * Z, c, a.n, dd, o);
+  for (int t = 0; t < SDC_NT; ++t) {
+#pragma unroll
+    for (int q = 0; q < SDC_NH; ++q) W[t][q] = a.Uf[(i64)q * Z + zt[t]];
   }
 #pragma unroll
   for (int q = 0; q < SDC_NH; ++q) {
@@ -1249,13 +1285,11 @@ __device__ __forceinline__ void flux4_body(const Flux4Args& a) {
   for (int q = 0; q < SDC_NH; ++q) a.F[(i64)q * Z + z] = F[q];
   // species: passive, flux u_n times the species density
   for (int s = 0; s < SDC_NS; ++s) {
-    const double* us = a.U + (i64)(SDC_NH + s) * Z;
+    const double* us = a.Uf + (i64)(SDC_NH + s) * Z;
     double v[SDC_NT], f[SDC_NT];
 #pragma unroll
     for (int t = 0; t < SDC_NT; ++t) {
-      int dd, o;
-      transverse<D>(t, dd, o);
-      v[t] = face_avg4<D>(us, c, a.n, dd, o);
+      v[t] = us[zt[t]];
       f[t] = v[t] * un[t];
     }
     const double vc = v[0] - cross_lap24(v);
@@ -1299,10 +1333,11 @@ extern "C" __global__ __launch_bounds__(256) void sdc_convert4(ConvArgs a) {
   if (z >= a.Z) return;
   int c[3];
   zone_coords(z, a.n, c);
+  const Nbr nb = neighbours(c, a.n);
   for (int q = 0; q < a.ncomp; ++q) {
     const double* u = a.src + (i64)q * a.Z;
     const double u0 = u[z];
-    a.dst[(i64)q * a.Z + z] = u0 + a.sign * (lap_sum(u, c, a.n, u0) / 24.0);
+    a.dst[(i64)q * a.Z + z] = u0 + a.sign * (lap_sum(u, nb, u0) / 24.0);
   }
 }
 
@@ -1314,11 +1349,12 @@ extern "C" __global__ __launch_bounds__(256) void sdc_source4_centre(O4Args a) {
   const i64 Z = a.Z;
   int c[3];
   zone_coords(z, a.n, c);
+  const Nbr nb = neighbours(c, a.n);
   double uc[SDC_NC];
   for (int q = 0; q < SDC_NC; ++q) {
     const double* u = a.U + (i64)q * Z;
     const double u0 = u[z];
-    uc[q] = u0 - lap_sum(u, c, a.n, u0) / 24.0;
+    uc[q] = u0 - lap_sum(u, nb, u0) / 24.0;
   }
   double ke = 0.0;
 #pragma unroll
@@ -1374,11 +1410,12 @@ extern "C" __global__ __launch_bounds__(256) void sdc_newton_inputs4(O4Args a) {
   const i64 Z = a.Z;
   int c[3];
   zone_coords(z, a.n, c);
+  const Nbr nb = neighbours(c, a.n);
   double rc[SDC_NC];
   for (int q = 0; q < SDC_NC; ++q) {
     const double* u = a.U + (i64)q * Z;
     const double u0 = u[z];
-    rc[q] = u0 - lap_sum(u, c, a.n, u0) / 24.0;
+    rc[q] = u0 - lap_sum(u, nb, u0) / 24.0;
   }
   double ke = 0.0;
 #pragma unroll
@@ -1398,10 +1435,11 @@ extern "C" __global__ __launch_bounds__(256) void sdc_average_store4(O4Args a) {
   const i64 Z = a.Z;
   int c[3];
   zone_coords(z, a.n, c);
+  const Nbr nb = neighbours(c, a.n);
   for (int i = 0; i < SDC_NX; ++i) {
     const double* r = a.R_c + (i64)i * Z;
     const double r0 = r[z];
-    const double ravg = r0 + lap_sum(r, c, a.n, r0) / 24.0;
+    const double ravg = r0 + lap_sum(r, nb, r0) / 24.0;
     a.R[(i64)i * Z + z] = ravg;
     const int q = i == SDC_NX - 1 ? 1 + SDC_DIM : SDC_NH + i;
     a.U[(i64)q * Z + z] = fma(a.dtm, ravg, a.U[(i64)q * Z + z]);

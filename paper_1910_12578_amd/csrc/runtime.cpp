@@ -493,9 +493,10 @@ struct sdc_handle_s {
   // face fluxes F [NC][Z], zone-centre density [Z], Newton rhs, iterate and
   // source [NX][Z] each, iteration counts [Z]
   hipFunction_t f_flux4[3] = {nullptr, nullptr, nullptr}, f_div4[3] = {nullptr, nullptr, nullptr},
+                f_favg4[3] = {nullptr, nullptr, nullptr},
                 f_conv4 = nullptr, f_source4c = nullptr, f_rhs4[3] = {nullptr, nullptr, nullptr},
                 f_newin4 = nullptr, f_avgst4 = nullptr;
-  double *o4_F = nullptr, *o4_rho = nullptr, *o4_b = nullptr, *o4_x = nullptr, *o4_R = nullptr;
+  double *o4_F = nullptr, *o4_Uf = nullptr, *o4_rho = nullptr, *o4_b = nullptr, *o4_x = nullptr, *o4_R = nullptr;
   int* o4_it = nullptr;
   // deferred-zone queue (capacity Z, allocated on first use) and the tuned
   // kernel choice: occupancy-2 variants and the fast-pass iteration cap
@@ -565,7 +566,7 @@ int fail(sdc_handle h, int code, const std::string& msg) {
 int kind_of(const sdc_handle h, hipFunction_t f) {
   if (f == h->f_advect || f == h->f_advect_rows) return SDC_K_ADVECT;
   for (int d = 0; d < 3; ++d)
-    if (f && (f == h->f_flux4[d] || f == h->f_div4[d])) return SDC_K_ADVECT;
+    if (f && (f == h->f_flux4[d] || f == h->f_div4[d] || f == h->f_favg4[d])) return SDC_K_ADVECT;
   if (f && (f == h->f_source4c || f == h->f_conv4)) return SDC_K_SOURCE;
   if (f && f == h->f_rhs4[0]) return SDC_K_TRANSITION_FIRST;
   if (f && f == h->f_rhs4[1]) return SDC_K_TRANSITION_NODE0;
@@ -690,6 +691,7 @@ int ensure_o4(sdc_handle h) {
   if (h->o4_F) return SDC_OK;
   const size_t Z = (size_t)h->P.Z;
   if (hipMalloc((void**)&h->o4_F, h->nc * Z * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&h->o4_Uf, h->nc * Z * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&h->o4_rho, Z * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&h->o4_b, h->nx * Z * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&h->o4_x, h->nx * Z * sizeof(double)) != hipSuccess ||
@@ -700,9 +702,9 @@ int ensure_o4(sdc_handle h) {
 }
 
 void free_o4(sdc_handle h) {
-  for (void* p : {(void*)h->o4_F, (void*)h->o4_rho, (void*)h->o4_b, (void*)h->o4_x, (void*)h->o4_R, (void*)h->o4_it})
+  for (void* p : {(void*)h->o4_F, (void*)h->o4_Uf, (void*)h->o4_rho, (void*)h->o4_b, (void*)h->o4_x, (void*)h->o4_R, (void*)h->o4_it})
     if (p) (void)hipFree(p);
-  h->o4_F = h->o4_rho = h->o4_b = h->o4_x = h->o4_R = nullptr;
+  h->o4_F = h->o4_Uf = h->o4_rho = h->o4_b = h->o4_x = h->o4_R = nullptr;
   h->o4_it = nullptr;
 }
 
@@ -802,6 +804,7 @@ int advect4(sdc_handle h, const double* U, double* A, hipStream_t s) {
   std::memset(&a, 0, sizeof a);
   a.U = U;
   a.F = h->o4_F;
+  a.Uf = h->o4_Uf;
   a.A = A;
   a.Z = h->P.Z;
   grid_extents(h, a.n);
@@ -809,6 +812,7 @@ int advect4(sdc_handle h, const double* U, double* A, hipStream_t s) {
   for (int d = 0; d < c.dim; ++d) {
     a.first = d == 0;
     a.idx = 1.0 / c.dx[d];
+    if (int rc = launch(h, h->f_favg4[d], h->P.Z, &a, s)) return rc;
     if (int rc = launch(h, h->f_flux4[d], h->P.Z, &a, s)) return rc;
     if (int rc = launch(h, h->f_div4[d], h->P.Z, &a, s)) return rc;
   }
@@ -1526,8 +1530,10 @@ int sdc_init(const sdc_config* cfg, const sdc_network* net, sdc_handle* out) {
     // fourth-order kernels (the flux and divergence kernels exist per direction)
     const char* f4[] = {"sdc_flux4_0", "sdc_flux4_1", "sdc_flux4_2"};
     const char* d4[] = {"sdc_div4_0", "sdc_div4_1", "sdc_div4_2"};
+    const char* a4[] = {"sdc_faceavg4_0", "sdc_faceavg4_1", "sdc_faceavg4_2"};
     for (int d = 0; d < h->P.cfg.dim; ++d) {
       if (hipModuleGetFunction(&h->f_flux4[d], h->mod, f4[d]) != hipSuccess ||
+          hipModuleGetFunction(&h->f_favg4[d], h->mod, a4[d]) != hipSuccess ||
           hipModuleGetFunction(&h->f_div4[d], h->mod, d4[d]) != hipSuccess)
         return bail(SDC_ERR_HIP, std::string("missing kernel ") + f4[d]);
     }
