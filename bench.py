@@ -546,7 +546,8 @@ def main():
         others["order4"] = dict(workload=workload_label(w4), zones=Z, **{k: summary(v) for k, v in r4.items()})
         del w4
     if not a.no_amr and a.space_order == 2 and a.node_type == "lobatto" and shape is None and w["dim"] == 3:
-        patches = [((32, 40, 48), (64, 64, 64)), ((150, 130, 120), (48, 64, 80))]
+        # x extents of 62 coarse zones: padded patch rows of 128 fine zones fill the row kernel's blocks
+        patches = [((32, 40, 48), (62, 64, 64)), ((150, 130, 120), (62, 64, 80))]
         print("[bench] refined patches", file=sys.stderr, flush=True)
         r = run_amr(w, patches, a.steps, a.warmup)
         others["amr"] = dict(workload=workload_label(w) + " coarse level, patches refined by 2 with subcycling", **r)
