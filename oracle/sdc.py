@@ -22,10 +22,15 @@ Readings where the paper is silent:
   KE taken from the new rho and rho u;
 * Newton starts from the reacting vector of U^{m+1,(k)} (the same node at the
   previous iteration), re-forms the analytic Jacobian every iteration, solves
-  with LU and partial pivoting (LAPACK via numpy.linalg.solve), and stops when
-  max_i |delta_i| / s_i <= tol with s = rho for species and |b_e| for the
-  energy; at least one iteration, at most maxiter, no damping or clipping;
-  a zone that does not converge keeps its last iterate and reports -1;
+  with LU and partial pivoting (LAPACK via numpy.linalg.solve), and measures
+  each step by e_k = max_i |delta_i| / s_i with s = rho for species and |b_e|
+  for the energy.  It stops after step k when e_k <= tol, or when the steps
+  contract (e_k < e_{k-1}) and the contraction bounds the new iterate's
+  distance from the root by tol: theta = e_k / e_{k-1}, and the distance is at
+  most theta / (1 - theta) e_k = e_k^2 / (e_{k-1} - e_k) <= tol (the stopping
+  test of Hairer and Wanner, Solving ODEs II, Sec. IV.8, with kappa = 1).  At
+  least one iteration, at most maxiter, no damping or clipping; a zone that
+  does not converge keeps its last iterate and reports -1;
 * R^{m+1,(k+1)} is R re-evaluated at the converged x;
 * A^0 and R^0 of step n+1 are A^{M,(K)} and R^{M,(K)} of step n (the same
   state; `run` carries them over).
@@ -177,6 +182,7 @@ def newton_solve(b, rho, dtm, x0, prob: Problem, chunk=32768):
                                 np.abs(bs[ns].real)[None]], axis=0)
         active = np.arange(rs.size)
         conv = np.zeros(rs.size, dtype=bool)
+        prev = np.zeros(rs.size)  # size of the previous step; 0 before the first
 
         def update(idx):
             xa = xs[:, idx]
@@ -191,7 +197,12 @@ def newton_solve(b, rho, dtm, x0, prob: Problem, chunk=32768):
             if active.size == 0:
                 break
             err = update(active)
-            done = err <= prob.newton_tol
+            p = prev[active]
+            tol = prob.newton_tol
+            # the step was small enough, or the contraction it shows bounds the
+            # distance of the new iterate from the root by tol
+            done = (err <= tol) | ((err < p) & (err * err <= tol * (p - err)))
+            prev[active] = err
             nu[start + active[done]] = it
             conv[active[done]] = True
             active = active[~done]
