@@ -104,7 +104,10 @@ typedef struct {
   int32_t advection;       /* 0: A == 0 (reaction only), 1: advective term on */
   int32_t slope;           /* 0: central slopes, 1: monotonized-central slopes */
   double alpha;            /* > 0: frozen Rusanov speed; <= 0: local max(|u| + c) */
-  double newton_tol;       /* stop when max_i |delta_i| / s_i <= tol (s = rho, |b_e|) */
+  double newton_tol;       /* Newton stops when its scaled step e_k = max_i |delta_i| / s_i
+                            * (s = rho, |b_e|) is <= tol, or when e_k < e_{k-1} and
+                            * e_k^2 / (e_{k-1} - e_k) <= tol (the contraction bounds the
+                            * distance of the new iterate from the root by tol) */
   int32_t newton_maxiter;  /* >= 1 */
   double pivot_threshold;  /* tau: a pivot below tau * column max takes the pivoted path */
   /* Batched boxes: nbox > 0 replaces the single grid by nbox independent
@@ -252,8 +255,8 @@ int sdc_reaction_solve(sdc_handle h, double dt_m, const double* rho, const doubl
  * queue lives in a fixed device array of SDC_NOALLOC_SCRATCH_BYTES inside the
  * library (one per device, held until the process ends), so the call makes no
  * hipMalloc, hipFree or other allocation and records no profiling events.
- * Limit: the queue needs 24 + 16 n_r bytes per zone (plus at most 2 KiB of
- * alignment), about 270,000 zones at n_r = 14; a larger nzones returns
+ * Limit: the queue needs 28 + 16 n_r bytes per zone (plus at most 2 KiB of
+ * alignment), about 266,000 zones at n_r = 14; a larger nzones returns
  * SDC_ERR_ARG (the message gives the limit).  nzones = 0 is a no-op.  Calls that overlap on
  * one device (concurrent streams, or handles on several threads) share that
  * device's array and race; calls serialised on one stream do not.  The queue

@@ -18,6 +18,7 @@ typedef struct {
 typedef struct {
   sdc_i64* z;         // [capacity] zone index
   int* it;            // [capacity] iterations done; -i: the pivot guard stopped iteration i
+  double* perr;       // [capacity] size of the last step taken (Newton's stopping test)
   double* x;          // [NX][capacity] current iterate
   double* b;          // [NX][capacity] right-hand side
   double* aux;        // [2 + DIM][capacity] rho, kinetic energy, momenta (transitions)

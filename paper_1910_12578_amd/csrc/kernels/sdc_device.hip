@@ -469,6 +469,15 @@ extern "C" __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
 #endif
 
 // ------------------------------------------------------------ reactions
+// Newton's stopping test on the scaled step sizes e_k = err and e_{k-1} =
+// perr (0 before the first step): the step is at most tol, or the steps
+// contract and the contraction bounds the new iterate's distance from the
+// root, theta / (1 - theta) e_k with theta = e_k / e_{k-1}, by tol (Hairer and
+// Wanner, Solving ODEs II, Sec. IV.8).
+__device__ __forceinline__ bool newton_done(double err, double perr, double tol) {
+  return err <= tol || (err < perr && err * err <= tol * (perr - err));
+}
+
 struct VecX {
   double v[SDC_NX];
 };
@@ -515,7 +524,8 @@ __device__ __forceinline__ void dense_newton_matrix(const double* x, const doubl
 // that its arrays live in scratch memory and the fast path's register budget
 // does not pay for it.
 __device__ __attribute__((noinline)) DenseResult dense_newton(VecX xv, VecX bv, double rho, double dtm, ParamPtr P,
-                                                              double gm1, double tol, int it0, int maxiter) {
+                                                              double gm1, double tol, int it0, int maxiter,
+                                                              double perr) {
   DenseResult out;
   double x[SDC_NX], b[SDC_NX];
   for (int i = 0; i < SDC_NX; ++i) {
@@ -567,10 +577,11 @@ __device__ __attribute__((noinline)) DenseResult dense_newton(VecX xv, VecX bv, 
       inf_or_nan += r[k] * 0.0;
     }
     if (!(inf_or_nan == 0.0)) break;
-    if (err <= tol) {
+    if (newton_done(err, perr, tol)) {
       out.it = it;
       break;
     }
+    perr = err;
   }
   for (int i = 0; i < SDC_NX; ++i) out.x.v[i] = x[i];
   return out;
@@ -585,17 +596,20 @@ struct LdsVec {
 };
 
 // Fast Newton pass for x - dt_m R(x; rho) = b from the iterate in x, running
-// iterations it0..itmax.  Stops when max_i |delta_i| / s_i <= tol (s = rho for
-// species, |b_e| for energy).  Returns the last iteration index and a status:
+// iterations it0..itmax.  Measures each step by max_i |delta_i| / s_i (s = rho
+// for species, |b_e| for energy) and stops by newton_done.  Returns the last
+// iteration index and a status:
 // 0 converged, 1 no convergence by itmax, 2 the pivot guard stopped iteration
 // `it` before it changed x, 3 non-finite step.  MT is the type of the Newton
 // matrix and its LU factors (double, or float in the mixed mode where the
 // residual and the update stay in double).  No calls.  b is read back
-// unchanged from LDS at the end.
+// unchanged from LDS at the end.  perr: size of the step before iteration it0
+// (0: none); on return that of the last step taken (a step the pivot guard
+// rejected does not count).
 template <class MT>
 __device__ __forceinline__ int newton_fast(double* x, double* b, double irho, double ise, double dtm,
                                            ParamPtr P, double gm1, double tol, double tau, int it0, int itmax,
-                                           int& st) {
+                                           int& st, double& perr) {
   // x and b wait in LDS while the Newton matrix and its factors hold the
   // registers; each iteration reads them back where it needs them
   __shared__ double sh_x[SDC_NX][256], sh_b[SDC_NX][256];
@@ -643,10 +657,11 @@ __device__ __forceinline__ int newton_fast(double* x, double* b, double irho, do
       st = 3;
       break;
     }
-    if (err <= tol) {
+    if (newton_done(err, perr, tol)) {
       st = 0;
       break;
     }
+    perr = err;
   }
   asm volatile("" ::: "memory");
 #pragma unroll
@@ -671,16 +686,17 @@ __device__ __forceinline__ long long defer_slot(unsigned* count, bool want) {
 }
 
 // Finish a deferred solve: the fast pass from iteration it0 + 1 (it0 > 0) or
-// the dense pivoted Newton from iteration -it0 (it0 < 0, guard failure).
+// the dense pivoted Newton from iteration -it0 (it0 < 0, guard failure);
+// perr is the size of the last step taken before.
 template <class MT>
 __device__ __forceinline__ int newton_finish(double* x, double* b, double rho, double dtm, ParamPtr P, double gm1,
-                                             const NewtonCtl& ctl, int it0, int& fallbacks) {
+                                             const NewtonCtl& ctl, int it0, double perr, int& fallbacks) {
   const double irho = 1.0 / rho;
   const double ise = 1.0 / fabs(b[SDC_NX - 1]);
   int start = -it0;
   if (it0 > 0) {
     int st = 1;
-    const int it = newton_fast<MT>(x, b, irho, ise, dtm, P, gm1, ctl.tol, ctl.tau, it0 + 1, ctl.maxiter, st);
+    const int it = newton_fast<MT>(x, b, irho, ise, dtm, P, gm1, ctl.tol, ctl.tau, it0 + 1, ctl.maxiter, st, perr);
     if (st == 0) return it;
     if (st != 2) return -1;
     start = it;
@@ -692,7 +708,7 @@ __device__ __forceinline__ int newton_finish(double* x, double* b, double rho, d
     xv.v[i] = x[i];
     bv.v[i] = b[i];
   }
-  const DenseResult r = dense_newton(xv, bv, rho, dtm, P, gm1, ctl.tol, start, ctl.maxiter);
+  const DenseResult r = dense_newton(xv, bv, rho, dtm, P, gm1, ctl.tol, start, ctl.maxiter, perr);
 #pragma unroll
   for (int i = 0; i < SDC_NX; ++i) x[i] = r.x.v[i];
   return r.it;
@@ -714,6 +730,7 @@ __device__ __forceinline__ void reaction_solve_body(const SolveArgs& a) {
   ParamPtr P = stage_params(a.P);
   double x[SDC_NX], b[SDC_NX], rho = 1.0;
   int it = 0, st = 3;
+  double perr = 0.0;
   if (valid) {
 #pragma unroll
     for (int i = 0; i < SDC_NX; ++i) {
@@ -723,7 +740,7 @@ __device__ __forceinline__ void reaction_solve_body(const SolveArgs& a) {
     rho = a.rho[z];
     const double ise = 1.0 / fabs(b[SDC_NX - 1]);
     it = newton_fast<MT>(x, b, 1.0 / rho, ise, a.dtm, P, a.gm1, a.ctl.tol, a.ctl.tau, 1,
-                         min(a.ctl.cap, a.ctl.maxiter), st);
+                         min(a.ctl.cap, a.ctl.maxiter), st, perr);
   }
   const bool defer = valid && (st == 2 || (st == 1 && a.ctl.cap < a.ctl.maxiter));
   const long long slot = defer_slot(a.q.count, defer);
@@ -733,6 +750,7 @@ __device__ __forceinline__ void reaction_solve_body(const SolveArgs& a) {
     const i64 cap = a.q.capacity;
     a.q.z[slot] = z;
     a.q.it[slot] = st == 2 ? -it : it;
+    a.q.perr[slot] = perr;
 #pragma unroll
     for (int i = 0; i < SDC_NX; ++i) {
       a.q.x[(i64)i * cap + slot] = x[i];
@@ -775,7 +793,7 @@ __device__ __forceinline__ void reaction_finish_body(const SolveArgs& a) {
         b[k] = a.q.b[(i64)k * cap + i];
       }
       const double rho = a.q.aux[i];
-      nu = newton_finish<MT>(x, b, rho, a.dtm, P, a.gm1, a.ctl, a.q.it[i], fb);
+      nu = newton_finish<MT>(x, b, rho, a.dtm, P, a.gm1, a.ctl, a.q.it[i], a.q.perr[i], fb);
       double R[SDC_NX];
       net_source(x, 1.0 / rho, P, a.gm1, R);
 #pragma unroll
@@ -966,6 +984,7 @@ __device__ __forceinline__ void transition_body(const TransArgs& a) {
   double rho = 1.0, ke = 0.0, mom[SDC_DIM];
   double b[SDC_NX], x[SDC_NX];
   int it = 0, st = 3;
+  double perr = 0.0;
   if (valid) {
     // the m = 0 prologue (the quadrature inputs of every node) issues its
     // loads ahead of the other wave's Newton work (measured: helps the m = 0
@@ -977,7 +996,7 @@ __device__ __forceinline__ void transition_body(const TransArgs& a) {
     for (int s = 0; s < SDC_NS; ++s) x[s] = ld_s(&a.guess[(i64)(SDC_NH + s) * Z + z]);
     if (KIND == KIND_NODE0) __builtin_amdgcn_s_setprio(0);
     it = newton_fast<MT>(x, b, 1.0 / rho, 1.0 / fabs(b[SDC_NX - 1]), a.dtm, P, a.gm1, a.ctl.tol, a.ctl.tau, 1,
-                         min(a.ctl.cap, a.ctl.maxiter), st);
+                         min(a.ctl.cap, a.ctl.maxiter), st, perr);
   }
   const bool defer = valid && (st == 2 || (st == 1 && a.ctl.cap < a.ctl.maxiter));
   const long long slot = defer_slot(a.q.count, defer);
@@ -987,6 +1006,7 @@ __device__ __forceinline__ void transition_body(const TransArgs& a) {
     const i64 cap = a.q.capacity;
     a.q.z[slot] = z;
     a.q.it[slot] = st == 2 ? -it : it;
+    a.q.perr[slot] = perr;
 #pragma unroll
     for (int i = 0; i < SDC_NX; ++i) {
       a.q.x[(i64)i * cap + slot] = x[i];
@@ -1027,7 +1047,7 @@ __device__ __forceinline__ void transition_finish_body(const TransArgs& a) {
       const double rho = a.q.aux[i], ke = a.q.aux[cap + i];
 #pragma unroll
       for (int d = 0; d < SDC_DIM; ++d) mom[d] = a.q.aux[(i64)(2 + d) * cap + i];
-      nu = newton_finish<MT>(x, b, rho, a.dtm, P, a.gm1, a.ctl, a.q.it[i], fb);
+      nu = newton_finish<MT>(x, b, rho, a.dtm, P, a.gm1, a.ctl, a.q.it[i], a.q.perr[i], fb);
       transition_store(a, z, rho, ke, mom, x, P);
       nonfinite = !all_finite(x);
     }
@@ -1069,6 +1089,7 @@ __device__ __forceinline__ void transition_newton_body(const TransArgs& a) {
   double rho = 1.0, ke = 0.0;
   double b[SDC_NX], x[SDC_NX];
   int it = 0, st = 3;
+  double perr = 0.0;
   if (valid) {
     rho = a.Uout[z];
     ke = a.split[(i64)SDC_NX * Z + z];
@@ -1078,7 +1099,7 @@ __device__ __forceinline__ void transition_newton_body(const TransArgs& a) {
     for (int s = 0; s < SDC_NS; ++s) x[s] = a.guess[(i64)(SDC_NH + s) * Z + z];
     x[SDC_NX - 1] = a.split[(i64)(SDC_NX + 1) * Z + z];
     it = newton_fast<MT>(x, b, 1.0 / rho, 1.0 / fabs(b[SDC_NX - 1]), a.dtm, P, a.gm1, a.ctl.tol, a.ctl.tau, 1,
-                         min(a.ctl.cap, a.ctl.maxiter), st);
+                         min(a.ctl.cap, a.ctl.maxiter), st, perr);
   }
   const bool defer = valid && (st == 2 || (st == 1 && a.ctl.cap < a.ctl.maxiter));
   const long long slot = defer_slot(a.q.count, defer);
@@ -1088,6 +1109,7 @@ __device__ __forceinline__ void transition_newton_body(const TransArgs& a) {
     const i64 cap = a.q.capacity;
     a.q.z[slot] = z;
     a.q.it[slot] = st == 2 ? -it : it;
+    a.q.perr[slot] = perr;
 #pragma unroll
     for (int i = 0; i < SDC_NX; ++i) {
       a.q.x[(i64)i * cap + slot] = x[i];

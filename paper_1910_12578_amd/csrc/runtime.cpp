@@ -66,12 +66,12 @@ void* scratch_address(int dev, hipError_t* rc) {
 }
 
 // Deferred-zone queue of `cap` zones carved from a scratch block of `bytes`
-// (256-byte aligned pieces: counter, zone index, iteration, x, b, rho).
-// Returns the bytes used, or -1 if they exceed `bytes`.
+// (256-byte aligned pieces: counter, zone index, iteration, x, b, rho, last
+// step size).  Returns the bytes used, or -1 if they exceed `bytes`.
 int64_t carve_queue(unsigned char* base, int64_t bytes, int64_t cap, int nx, DeferQueue* q) {
   auto up = [](int64_t v) { return (v + 255) & ~int64_t(255); };
   const int64_t o_z = 256, o_it = o_z + up(cap * 8), o_x = o_it + up(cap * 4), o_b = o_x + up(cap * 8 * nx),
-                o_aux = o_b + up(cap * 8 * nx), end = o_aux + up(cap * 8);
+                o_aux = o_b + up(cap * 8 * nx), o_pe = o_aux + up(cap * 8), end = o_pe + up(cap * 8);
   if (end > bytes) return -1;
   q->count = (unsigned*)base;
   q->z = (sdc_i64*)(base + o_z);
@@ -79,6 +79,7 @@ int64_t carve_queue(unsigned char* base, int64_t bytes, int64_t cap, int nx, Def
   q->x = (double*)(base + o_x);
   q->b = (double*)(base + o_b);
   q->aux = (double*)(base + o_aux);
+  q->perr = (double*)(base + o_pe);
   q->capacity = cap;
   return end;
 }
@@ -648,6 +649,7 @@ int ensure_queue(sdc_handle h) {
       hipMalloc((void**)&q.x, (size_t)h->nx * Z * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&q.b, (size_t)h->nx * Z * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&q.aux, aux * Z * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&q.perr, Z * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&q.count, sizeof(unsigned)) != hipSuccess)
     return fail(h, SDC_ERR_NOMEM, "hipMalloc(deferred-zone queue) failed");
   h->q_ready = true;
@@ -681,7 +683,7 @@ void free_split(sdc_handle h) {
 
 void free_queue(sdc_handle h) {
   DeferQueue& q = h->q;
-  for (void* p : {(void*)q.z, (void*)q.it, (void*)q.x, (void*)q.b, (void*)q.aux, (void*)q.count})
+  for (void* p : {(void*)q.z, (void*)q.it, (void*)q.x, (void*)q.b, (void*)q.aux, (void*)q.perr, (void*)q.count})
     if (p) (void)hipFree(p);
   h->q = DeferQueue{};
   h->q_ready = false;
@@ -1682,7 +1684,7 @@ int sdc_reaction_solve_noalloc(sdc_handle h, double dt_m, int64_t nzones, const 
   SolveArgs a;
   std::memset(&a, 0, sizeof a);
   if (carve_queue((unsigned char*)h->scratch, SDC_NOALLOC_SCRATCH_BYTES, nzones, h->nx, &a.q) < 0) {
-    const int64_t per = 8 + 4 + 16 * (int64_t)h->nx + 8;
+    const int64_t per = 8 + 4 + 16 * (int64_t)h->nx + 8 + 8;
     return fail(h, SDC_ERR_ARG, "nzones = " + std::to_string(nzones) + " exceeds the scratch array of " +
                                     std::to_string((long long)SDC_NOALLOC_SCRATCH_BYTES) + " bytes (about " +
                                     std::to_string((SDC_NOALLOC_SCRATCH_BYTES - 2048) / per) + " zones at " +
