@@ -271,15 +271,18 @@ def reflux(Uc, Fc, Ff, p: Patch, hier: Hierarchy):
 
 def composite_totals(Uc, Ufs, hier: Hierarchy):
     """Sums of rho, rho u_d and rho E + q . rho X over the composite grid
-    (uncovered coarse zones and patch interiors), weighted by zone volume."""
+    (uncovered coarse zones and patch interiors), weighted by zone volume.
+    Accumulated in extended precision: on grids of 10^7 zones the rounding of
+    float64 sums alone reaches 1e-13 of the totals, above the conservation
+    they are meant to show."""
     pc = hier.prob
     d = pc.dim
-    q = pc.net["q"]
-    dVc = float(np.prod(pc.dx[:d]))
+    q = np.asarray(pc.net["q"], dtype=np.longdouble)
+    dVc = np.longdouble(np.prod(pc.dx[:d]))
     dVf = dVc / RATIO ** d
 
     def rows(U):
-        Uf = U.reshape(U.shape[0], -1)
+        Uf = U.reshape(U.shape[0], -1).astype(np.longdouble)
         return np.concatenate([Uf[:1 + d], (Uf[1 + d] + q @ Uf[2 + d:])[None]], axis=0)
 
     covered = np.zeros(Uc.shape[1:], dtype=bool)

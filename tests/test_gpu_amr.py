@@ -115,7 +115,7 @@ def test_composite_conservation_on_a_large_grid():
     a.step(w["dt"], 5, Uc, Uf)
     drift = np.abs(totals() - t0) / scale
     print("composite drift", drift)
-    assert np.all(drift <= 1e-13), drift
+    assert np.all(drift <= 1e-15), drift
     for st in a.stats():
         assert st["failed"] == 0 and st["nonfinite"] == 0
     a.close()

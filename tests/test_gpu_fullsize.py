@@ -113,6 +113,88 @@ def test_net3d_256cubed_sampled_windows(net3d_full, precision, tol, schedule):
     assert np.all(drift <= 1e-13), drift
 
 
+def test_net3d_256cubed_fourth_order_sampled_windows():
+    """The fourth-order leg at its full size (256^3 x 13 species, one step in
+    the tuned schedule the bench times) against the oracle's fourth-order
+    step on two 41^3 windows (core 9^3 each), and global conservation.  A
+    fourth-order evaluation of A reaches 2 zones along a direction (face
+    averages over 4 zones) and 1 across it, and the centre/average
+    conversions 1 zone, so one step stays within the same 16-zone radius
+    (a single-zone perturbation moves 8 zones in one step of the oracle)."""
+    import torch
+    from paper_1910_12578_amd import SDC, config_from_workload
+    w = dict(si.workload("net3d"), space_order=4)
+    W = RADIUS + 4
+    centres = [(200, 31, 5), (255, 0, 128)]
+    refs = []
+    for c in centres:
+        win, idx = window(w["U0"], c, W)
+        prob = osdc.Problem.from_workload(dict(w, shape=(2 * W + 1,) * 3))
+        out = osdc.run(win, w["dt"], 1, prob)
+        lin, sl = core_zones(idx, W, w["shape"])
+        refs.append((lin, out[:, sl, sl, sl].reshape(out.shape[0], -1)))
+    nc = w["U0"].shape[0]
+    with SDC(config_from_workload(w, autotune=1), w["network"]) as h:
+        U0g = torch.from_numpy(w["U0"].reshape(nc, -1)).to("cuda")
+        U = U0g.clone()
+        h.step(w["dt"], 1, U)
+        torch.cuda.synchronize()
+        st = h.stats()
+    assert st["failed"] == 0 and st["nonfinite"] == 0
+    for lin, ref in refs:
+        got = U[:, torch.from_numpy(lin).to("cuda")].cpu().numpy()
+        err = np.abs(got - ref).max(axis=1) / np.abs(ref).max(axis=1)
+        print(f"fourth order: core max rel err per component {err.max():.3e}")
+        assert np.all(err <= TOL_FP64), err
+    q = torch.tensor(w["network"]["q"], dtype=torch.float64)
+    before, after = conserved_totals(U0g, 3, q), conserved_totals(U, 3, q)
+    scale = np.array([float(U0g[c].abs().sum()) for c in range(4)] + [float(U0g[4].abs().sum())])
+    drift = np.abs(after - before) / scale
+    print("conservation drift (rho, rho u, rho E + q.rho X):", drift)
+    assert np.all(drift <= 1e-13), drift
+
+
+def test_refined_patches_at_the_bench_size_conserve():
+    """The refined-patch leg at its full size: the 256^3 coarse level with the
+    bench's two patches refined by 2 (about 4.2e6 fine zones), two coarse
+    steps with subcycling in the tuned schedule; the composite-grid mass,
+    momentum and total energy stay constant to rounding (the refluxing), and
+    every solve converges."""
+    import torch
+    from oracle import amr as oamr
+    from paper_1910_12578_amd import AMR, config_from_workload
+    w = si.workload("net3d")
+    patches = [((32, 40, 48), (62, 64, 64)), ((150, 130, 120), (62, 64, 80))]
+    nc = w["U0"].shape[0]
+    a = AMR(config_from_workload(w, autotune=1), w["network"], patches)
+    try:
+        Uc = torch.from_numpy(w["U0"].reshape(nc, -1)).to("cuda")
+        Uf = torch.empty((nc, a.zf), dtype=torch.float64, device="cuda")
+        a.fill_patches(Uc, Uf)
+        hier = oamr.Hierarchy(osdc.Problem.from_workload(w), [oamr.Patch(lo, ext) for lo, ext in patches])
+
+        def totals(f=lambda v: v):
+            Ucn = f(Uc.cpu().numpy().reshape(w["U0"].shape))
+            Ufn, off, Ufs = f(Uf.cpu().numpy()), 0, []
+            for p in hier.patches:
+                shp = tuple(2 * e + 4 for e in p.ext)[::-1]
+                n = int(np.prod(shp))
+                Ufs.append(Ufn[:, off:off + n].reshape((nc,) + shp))
+                off += n
+            return oamr.composite_totals(Ucn, Ufs, hier)
+
+        t0, scale = totals(), totals(np.abs)
+        a.step(w["dt"], 2, Uc, Uf)
+        torch.cuda.synchronize()
+        drift = np.abs(totals() - t0) / scale
+        print("composite drift", drift)
+        assert np.all(drift <= 1e-15), drift
+        for st in a.stats():
+            assert st["failed"] == 0 and st["nonfinite"] == 0
+    finally:
+        a.close()
+
+
 def test_net2d_512sq_sampled_windows():
     """512^2 x 7 species (zone-per-thread advective kernel), FP64 and mixed,
     against the oracle on four 49^2 windows (core 17^2 each)."""
