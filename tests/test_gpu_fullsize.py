@@ -156,7 +156,7 @@ def test_net3d_256cubed_fourth_order_sampled_windows():
 
 def test_refined_patches_at_the_bench_size_conserve():
     """The refined-patch leg at its full size: the 256^3 coarse level with the
-    bench's two patches refined by 2 (about 4.2e6 fine zones), two coarse
+    bench's two patches refined by 2 (about 4.6e6 fine zones), two coarse
     steps with subcycling in the tuned schedule; the composite-grid mass,
     momentum and total energy stay constant to rounding (the refluxing), and
     every solve converges."""
