@@ -203,10 +203,14 @@ def kernel_table(h, w, st, prof, sched, precision):
         row = dict(ms=round(ms, 3), launches=n, avg_ms=round(ms / n, 4), share=round(ms / total, 4))
         if k in bpz:
             r = roofline(bpz[k], fpz.get(k, 0.0), Z, ms * 1e-3 / n)
-            row.update(bytes_per_zone=bpz[k], hbm_frac=round(r["hbm_frac"], 4), fp64_frac=round(r["alu_frac"], 4))
+            # flops are counted only where the model has them (null otherwise)
+            row.update(bytes_per_zone=bpz[k], hbm_frac=round(r["hbm_frac"], 4),
+                       fp64_frac=round(r["alu_frac"], 4) if k in fpz else None)
         table[k] = row
     dom = max(table, key=lambda k: table[k]["ms"])
     roof = roofline(bpz[dom], fpz.get(dom, 0.0), Z, prof[dom][0] * 1e-3 / prof[dom][1])
+    if dom not in fpz:
+        roof.update(alu_frac=None, alu_TFLOPs=None)
     kname = kernel_name(dom, w["dim"], sched, precision, w.get("space_order", 2))
     roof["traffic"], digest = recorded_traffic(h, kname)
     roof["kernel"] = kname
