@@ -163,7 +163,8 @@ typedef struct {
  * SDC step (the extension to adaptive mesh refinement that Sec. 2 and Sec. 5
  * name).  Level 0 is the periodic coarse grid of `coarse`; every patch is a
  * box of coarse zones (lo, ext per direction, x y z; inside the grid, two or
- * more coarse zones from every other patch) refined by 2 in space and time.
+ * more coarse zones from every other patch and from itself, also across the
+ * periodic boundary) refined by 2 in space and time.
  * Patch arrays are padded by 2 ghost zones per side and concatenated in patch
  * order, each x fastest, SoA [n_c][Zf] (the layout of batched boxes with
  * extents 2 ext + 4).  A coarse step of length dt: the coarse level takes one

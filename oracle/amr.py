@@ -8,8 +8,9 @@ around the SDC step of sdc.py:
 
 * Levels.  Level 0 is the periodic coarse grid.  Level 1 is a set of patches,
   each a box of coarse zones refined by r = 2 in every direction, two or more
-  coarse zones apart from each other, stored with G = 2 ghost zones per side
-  (the stencil radius of A), x fastest.
+  coarse zones apart from each other and from itself across the periodic
+  boundary (so every coarse zone next to a patch is uncovered), stored with
+  G = 2 ghost zones per side (the stencil radius of A), x fastest.
 * A coarse step of length dt:
   1. the coarse level takes one SDC step on the whole grid, covered zones
      included;
@@ -77,9 +78,15 @@ class Hierarchy:
             for e in range(d):
                 if p.ext[e] < 1 or p.lo[e] < 0 or p.lo[e] + p.ext[e] > prob.shape[e]:
                     raise ValueError("patch must lie inside the coarse grid")
+                if p.ext[e] + 2 > prob.shape[e]:
+                    raise ValueError("a patch must leave two coarse zones uncovered along every direction")
         for i, a in enumerate(self.patches):
             for b in self.patches[i + 1:]:
-                apart = any(a.lo[e] + a.ext[e] + 2 <= b.lo[e] or b.lo[e] + b.ext[e] + 2 <= a.lo[e] for e in range(d))
+                # gaps of two or more zones on both sides of the periodic grid, along some direction
+                n = prob.shape
+                apart = any((a.lo[e] + a.ext[e] + 2 <= b.lo[e] and b.lo[e] + b.ext[e] + 2 <= a.lo[e] + n[e]) or
+                            (b.lo[e] + b.ext[e] + 2 <= a.lo[e] and a.lo[e] + a.ext[e] + 2 <= b.lo[e] + n[e])
+                            for e in range(d))
                 if not apart:
                     raise ValueError("patches must be two or more coarse zones apart")
 

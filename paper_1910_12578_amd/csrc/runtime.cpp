@@ -2099,14 +2099,19 @@ int sdc_amr_create(const sdc_config* coarse, const sdc_network* net, const sdc_p
     for (int d = 0; d < dim; ++d) {
       const int64_t l = patches->lo[3 * p + d], e = patches->ext[3 * p + d];
       if (e < 1 || l < 0 || l + e > cc.n[d]) return fail(nullptr, SDC_ERR_ARG, "patch must lie inside the coarse grid");
+      if (e + 2 > cc.n[d])
+        return fail(nullptr, SDC_ERR_ARG, "a patch must leave two coarse zones uncovered along every direction");
     }
   for (int p = 0; p < np; ++p)
     for (int q = p + 1; q < np; ++q) {
+      // gaps of two or more coarse zones on both sides of the periodic grid,
+      // along some direction, so that every coarse zone next to a patch is
+      // uncovered (its reflux target)
       bool apart = false;
       for (int d = 0; d < dim; ++d) {
         const int64_t lp = patches->lo[3 * p + d], ep = patches->ext[3 * p + d];
-        const int64_t lq = patches->lo[3 * q + d], eq = patches->ext[3 * q + d];
-        apart = apart || lp + ep + 2 <= lq || lq + eq + 2 <= lp;
+        const int64_t lq = patches->lo[3 * q + d], eq = patches->ext[3 * q + d], n = cc.n[d];
+        apart = apart || (lp + ep + 2 <= lq && lq + eq + 2 <= lp + n) || (lq + eq + 2 <= lp && lp + ep + 2 <= lq + n);
       }
       if (!apart) return fail(nullptr, SDC_ERR_ARG, "patches must be two or more coarse zones apart");
     }

@@ -128,5 +128,10 @@ def test_hierarchy_rejects_bad_patches():
         AMR(config_from_workload(w), w["network"], [((2, 2), (4, 4)), ((7, 2), (3, 3))])  # one zone apart
     with pytest.raises(SDCError, match="SDC_ERR_ARG"):
         AMR(config_from_workload(w), w["network"], [((14, 2), (4, 4))])  # past the grid
+    with pytest.raises(SDCError, match="SDC_ERR_ARG"):  # one zone apart across the periodic boundary
+        AMR(config_from_workload(w), w["network"], [((1, 2), (4, 4)), ((8, 2), (8, 4))])
+    with pytest.raises(SDCError, match="SDC_ERR_ARG"):  # meets itself across it
+        AMR(config_from_workload(w), w["network"], [((0, 2), (15, 4))])
+    AMR(config_from_workload(w), w["network"], [((2, 2), (4, 4)), ((8, 2), (6, 4))]).close()  # two zones apart both ways
     with pytest.raises(SDCError, match="SDC_ERR_UNSUPPORTED"):
         AMR(config_from_workload(w, space_order=4), w["network"], [((2, 2), (4, 4))])

@@ -184,3 +184,16 @@ def test_two_level_run_converges_to_the_uniformly_fine_run():
     print("patch errors", e_fine, "orders", o, "uncovered", e_coarse, "plain coarse", e_plain)
     assert o[-1] > 1.9, (e_fine, o)
     assert np.all(np.array(e_coarse) <= 1.2 * np.array(e_plain))
+
+
+def test_patches_meeting_across_the_periodic_boundary_are_rejected():
+    """Patches two zones apart inside the grid but touching through the
+    periodic boundary, and a patch that meets itself through it, would make
+    a covered coarse zone the reflux target of an interface face."""
+    net = si.chain_network()
+    pc = problem((16, 12), (1 / 16, 1 / 12), net)
+    amr.Hierarchy(pc, [amr.Patch((2, 2), (4, 4)), amr.Patch((8, 2), (6, 4))])  # 2 zones apart both ways
+    with pytest.raises(ValueError, match="apart"):
+        amr.Hierarchy(pc, [amr.Patch((1, 2), (4, 4)), amr.Patch((8, 2), (8, 4))])  # one zone apart across x = 0
+    with pytest.raises(ValueError, match="uncovered"):
+        amr.Hierarchy(pc, [amr.Patch((0, 2), (15, 4))])
