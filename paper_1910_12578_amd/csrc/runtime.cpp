@@ -1310,7 +1310,7 @@ int autotune(sdc_handle h, double dt, const double* U, const sdc_nodes& n, hipSt
   HIP_CHECK(h, hipEventCreate(&e1));
   // the split schedule is not searched: it moves more bytes and measured
   // slower than the fused kernels on the 3D workloads
-  const int caps[] = {0, 4, 5, 6}, splits[] = {0};
+  const int caps[] = {0, 2, 3, 4, 5, 6}, splits[] = {0};
   float best = 1e30f;
   int bo = 0, bc = 0, bs = 0;
   for (int rep = 0; rep < 2 && rc == SDC_OK; ++rep)  // the first pass warms caches and clocks
