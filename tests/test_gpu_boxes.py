@@ -73,4 +73,4 @@ def test_lognormal_temperature_spreads_newton_counts():
     hist = np.array(h.stats()["hist"])
     used = np.nonzero(hist)[0]
     print("Newton histogram", dict(zip(used.tolist(), hist[used].tolist())))
-    assert used.max() - used.min() >= 3
+    assert used.min() <= 2 and used.max() >= 7
