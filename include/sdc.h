@@ -343,7 +343,7 @@ int sdc_set_schedule(sdc_handle h, int32_t occ2, int32_t cap, int32_t split, int
 int sdc_get_schedule(sdc_handle h, int32_t* occ2, int32_t* cap, int32_t* split, int32_t* zchunk);
 
 /*
- * Time every fused schedule (occ2 in {0,1} x cap in {0,4,5,6}, split 0) on
+ * Time every fused schedule (occ2 in {0,1} x cap in {0,2,3,4,5,6}, split 0) on
  * one SDC step from U (read only; `work` is scratch) with HIP events on
  * `stream`, then the row-kernel tile (zchunk in {0, 16, 32, 64, 128}) on the
  * advective term of U; keep the fastest of each (the defaults unless another
