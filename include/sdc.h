@@ -211,7 +211,10 @@ int sdc_config_default(sdc_config* cfg);
  * Create a handle: validates the configuration, generates the network's
  * device code (rates, residual, packed Newton matrix and its fixed-order LU)
  * and compiles it with the kernels for gfx950 (cached on disk, see
- * SDC_KERNEL_CACHE), uploads the network parameters.
+ * SDC_KERNEL_CACHE), uploads the network parameters.  3D grids take the row
+ * advection kernel where their rows fit a block; SDC_ADVECT_ROWS=0 in the
+ * environment selects the zone-per-thread kernel instead (same fluxes, for
+ * comparison).
  * Errors: SDC_ERR_ARG, SDC_ERR_UNSUPPORTED, SDC_ERR_COMPILE, SDC_ERR_HIP,
  * SDC_ERR_NOMEM.  On error *out is NULL; sdc_last_error(NULL) explains.
  */
