@@ -122,3 +122,26 @@ def test_fourth_order_rejects_boxes_and_adjoint():
     with pytest.raises(SDCError, match="SDC_ERR_UNSUPPORTED"):
         h.step_adjoint(w["dt"], U, U.clone())
     h.close()
+
+
+def test_step4_schedules_bitwise_identical():
+    """The Newton schedules (register budget, iteration cap with the deferred
+    finish kernel) only move where a zone's iterations run, also in the
+    fourth-order transitions' centre solve: every one gives the default bits."""
+    import torch
+    w, prob, h = make("net2d")
+    nc = w["U0"].shape[0]
+
+    def one():
+        U = to_gpu(w["U0"].reshape(nc, -1))
+        h.stats_reset()
+        h.step(w["dt"], 2, U)
+        return U, h.stats()
+
+    ref, sref = one()
+    for sched in [(1, 0, 0, 0), (0, 1, 0, 0), (1, 2, 0, 0), (0, 3, 0, 0)]:
+        h.set_schedule(*sched)
+        U, s = one()
+        assert bool(torch.equal(U, ref)), sched
+        assert s == sref, sched
+    h.close()
