@@ -457,6 +457,11 @@ class AMR:
         _check(lib().sdc_amr_step(self._a, float(dt), int(nsteps), self._arr(Uc, self.zc), self._arr(Uf, self.zf),
                                   SDC._stream(stream)), self._hc)
 
+    def set_schedule(self, occ2=0, cap=0, split=0, zchunk=0):
+        """sdc_set_schedule on the coarse level; a step passes its Newton
+        schedule (occ2, cap) on to the patches."""
+        _check(lib().sdc_set_schedule(self._hc, int(occ2), int(cap), int(split), int(zchunk)), self._hc)
+
     def stats(self):
         out = []
         for h in (self._hc, self._hf):

@@ -135,3 +135,25 @@ def test_hierarchy_rejects_bad_patches():
     AMR(config_from_workload(w), w["network"], [((2, 2), (4, 4)), ((8, 2), (6, 4))]).close()  # two zones apart both ways
     with pytest.raises(SDCError, match="SDC_ERR_UNSUPPORTED"):
         AMR(config_from_workload(w, space_order=4), w["network"], [((2, 2), (4, 4))])
+
+
+def test_two_level_schedules_bitwise_identical():
+    """The coarse level's Newton schedule, which the patches take over, only
+    moves where iterations run: the two-level step gives the default bits."""
+    import torch
+    w, hier, a = setup("net3d")
+    nc = w["U0"].shape[0]
+
+    def one():
+        Uc = to_gpu(w["U0"].reshape(nc, -1))
+        Uf = torch.empty((nc, a.zf), dtype=torch.float64, device="cuda")
+        a.fill_patches(Uc, Uf)
+        a.step(w["dt"], 1, Uc, Uf)
+        return Uc, Uf
+
+    rc, rf = one()
+    for sched in [(1, 0), (0, 2), (1, 3)]:
+        a.set_schedule(*sched)
+        Uc, Uf = one()
+        assert bool(torch.equal(Uc, rc)) and bool(torch.equal(Uf, rf)), sched
+    a.close()
