@@ -74,3 +74,25 @@ def test_lognormal_temperature_spreads_newton_counts():
     used = np.nonzero(hist)[0]
     print("Newton histogram", dict(zip(used.tolist(), hist[used].tolist())))
     assert used.min() <= 2 and used.max() >= 7
+
+
+def test_box_schedules_bitwise_identical():
+    """Newton schedules and row-kernel tiles over the batched boxes (the
+    tiles cut each box's z extent into chunks of its own) give the default
+    bits, on boxes with spread Newton counts."""
+    import torch
+    w = small_boxes(nbox=12, choices=(4, 8, 12), seed=9)
+    h = make(w)
+
+    def one():
+        U = to_gpu(w["U0"])
+        h.stats_reset()
+        h.step(w["dt"], 1, U)
+        return U, h.stats()
+
+    ref, sref = one()
+    for sched in [(1, 0, 0, 0), (0, 2, 0, 0), (1, 3, 0, 4), (0, 0, 0, 2), (0, 0, 0, 16)]:
+        h.set_schedule(*sched)
+        U, s = one()
+        assert bool(torch.equal(U, ref)), sched
+        assert s == sref, sched
