@@ -454,6 +454,31 @@ def workload_label(w):
             f"{w['n_nodes']} {nodes} nodes, K={w['n_iters']}{order}")
 
 
+def advect_probe(edges):
+    """The advective term of the net3d recipe on small cubic grids, six
+    evaluations each (the row kernel), then a 1 GiB device copy: a program for
+    counter runs that compare the bytes the kernel fetches from beyond L2 with
+    the bytes it reads once (n_c x 8 per zone) on grids that fit in L2."""
+    import torch
+    from paper_1910_12578_amd import SDC, config_from_workload
+    for n in edges:
+        w = si.workload("net3d", shape=(n, n, n))
+        nc = w["U0"].shape[0]
+        U = torch.from_numpy(w["U0"].reshape(nc, -1)).to("cuda")
+        with SDC(config_from_workload(w), w["network"]) as h:
+            A = h.advective_term(U)
+            for _ in range(5):
+                h.advective_term(U, A)
+            torch.cuda.synchronize()
+        print(json.dumps(dict(grid=n, zones=n ** 3, bytes_read_once=n ** 3 * nc * 8, evaluations=6)), flush=True)
+    x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_bytes=8 << 27)), flush=True)
+
+
 def gpu_leg(w, steps, warmup, schedule, precisions=("fp64", "mixed")):
     """FP64 and mixed runs of one single-grid workload, summarised."""
     out = {}
@@ -498,11 +523,17 @@ def main():
                     help="schedule: 'auto' (tuned on the first warmup step) or 'OCC2,CAP[,SPLIT[,ZCHUNK]]', e.g. 0,0,0,16")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (calibrates HBM byte counters)")
+    ap.add_argument("--advect-probe", default="",
+                    help="only evaluate the advective term six times on each of these cubic grids (e.g. "
+                         "16,24,32,64; small enough to stay in L2) and copy 1 GiB, for byte-counter runs")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {a.gpus}); multi-GPU sharding is a design "
               f"note, not a measured path", file=sys.stderr)
         sys.exit(2)
+    if a.advect_probe:
+        advect_probe([int(v) for v in a.advect_probe.split(",")])
+        return
     shape = tuple(int(v) for v in a.shape.split(",")) if a.shape else None
     print(f"[bench] generating {a.workload} {shape or ''}", file=sys.stderr, flush=True)
     w = si.workload(a.workload, shape=shape)
